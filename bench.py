@@ -1,0 +1,122 @@
+"""Benchmark: MPdist distance-matrix cells per second on one MI355X.
+
+One step = the whole snippet-finding hot path on one series, resident in HBM:
+FP64 window statistics, the MPdist profile of every segment (eqs. 9-15), the
+greedy minimum-area snippet search, neighbours and frac (eqs. 6-8, 16-17).
+Workload: 100 000-point regime-switching series of 5 shapes, m=256, l=128,
+k=26, K=4.  cells = nseg * (m-l+1) * (n-l+1) distance-matrix entries.
+
+Prints one JSON line.  --gpus N with N > 1 is refused: this build drives one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+WORKLOAD = dict(name="regimes5_n100000", n=100_000, m=256, l=128, K=4)
+# Algorithmic VALU lane-operations per distance-matrix cell (see the design
+# notes): covariance update 2 FMA, correlation 2 MUL, column max 1, sliding
+# row max 1, k-th selection 2 (each cell feeds 2 of the 2w values per window).
+OPS_PER_CELL = 8
+# 256 CUs x 64 lanes x 2.4 GHz: VALU lane-operations per second (non-packed).
+PEAK_LANE_OPS = 256 * 64 * 2.4e9
+
+
+def cpu_baseline(x, m, l, k, nseg_sample=3):
+    """The FP64 oracle on a bounded sample of segments of the same workload."""
+    import oracle
+    try:
+        from threadpoolctl import threadpool_limits
+        limiter = threadpool_limits(limits=1)
+    except Exception:  # pragma: no cover
+        limiter = None
+    n = len(x)
+    w = m - l + 1
+    segs = list(range(0, n // m, max(1, (n // m) // nseg_sample)))[:nseg_sample]
+    t0 = time.perf_counter()
+    oracle.profile_set(x, m, l, k, segments=segs)
+    dt = time.perf_counter() - t0
+    if limiter is not None:
+        limiter.unregister() if hasattr(limiter, "unregister") else None
+    cells = len(segs) * w * (n - l + 1)
+    return dict(value=cells / dt, unit="cells/s", cores=1, kind="oracle",
+                sample=f"profiles of {len(segs)} of {n // m} segments ({cells:.3g} cells, "
+                       f"{dt:.1f} s), numpy FP64, BLAS limited to 1 thread")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py drives exactly one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2401_13680_amd import api, synth
+
+    n, m, l, K = WORKLOAD["n"], WORKLOAD["m"], WORKLOAD["l"], WORKLOAD["K"]
+    k = synth.default_k(m)
+    w = m - l + 1
+    nseg = n // m
+    cells = nseg * w * (n - l + 1)
+    x = synth.workload_series(WORKLOAD["name"])
+    T = torch.from_numpy(x).cuda()
+    ctx = api.context(0)
+    L = ctx.L
+
+    for _ in range(args.warmup):
+        api.snippets(T, m, l, K, k, ctx=ctx)
+    torch.cuda.synchronize()
+    L.pst_set_timing(ctx.h, 1)
+    lat, kms = [], []
+    import ctypes
+    ms = ctypes.c_float()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        s0 = time.perf_counter()
+        api.snippets(T, m, l, K, k, ctx=ctx)
+        lat.append((time.perf_counter() - s0) * 1e3)
+        ctx.check(L.pst_last_profile_ms(ctx.h, ctypes.byref(ms)))
+        kms.append(ms.value)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    L.pst_set_timing(ctx.h, 0)
+
+    ms_step = dt * 1e3 / args.steps
+    value = cells / (dt / args.steps)
+    k_ms = float(np.mean(kms))
+    achieved = OPS_PER_CELL * cells / (k_ms * 1e-3) / 1e12
+    peak = PEAK_LANE_OPS / 1e12
+    out = dict(
+        metric="MPdist distance-matrix cells/sec on 1 MI355X; p50/p99 request latency",
+        value=value, unit="cells/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
+        ms_per_step=ms_step, higher_is_better=True, scaling="weak", vs_baseline=None,
+        dtype="f32", data="synthetic",
+        config=dict(workload=WORKLOAD["name"], n=n, m=m, l=l, k=k, K=K, cells_per_step=cells,
+                    step="stats + all segment profiles + greedy + neighbours"),
+        latency_ms=dict(p50=float(np.percentile(lat, 50)), p99=float(np.percentile(lat, 99))),
+        roofline=dict(bound="alu", achieved=achieved, peak=peak, unit="Tops/s (VALU lane-ops)",
+                      frac=achieved / peak, traffic=None, kernel="k_profile",
+                      kernel_ms=k_ms, ops_per_cell=OPS_PER_CELL),
+    )
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(x, m, l, k)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,139 @@
+/*
+ * pst.h -- C ABI of the MI355X MPdist-profile / snippet library.
+ *
+ * The library computes, on one gfx950 GPU, the snippet-finding hot path of
+ * the PaSTiLa method (Goglachev 2023, "a parallel algorithm for automated
+ * labelling of large time series"):
+ *
+ *   - MPdist profiles of a query, and of every segment, against a series
+ *     (section 4.1, eqs. 9-15),
+ *   - greedy minimum-area snippet selection with neighbours and frac
+ *     (section 3.2, eqs. 5-8; section 4.1, eqs. 16-17),
+ *   - the snippet-length criterion over candidate lengths (section 4.2, eq. 18).
+ *
+ * Conventions
+ *   - Every index is 0-based (the paper is 1-based).  A snippet's index is its
+ *     segment number s; the segment starts at element s*m (eq. 4).
+ *   - n: series length; m: segment / snippet length; l: MPdist sub-length;
+ *     w = m-l+1; nseg = floor(n/m) (the tail after the last whole segment is
+ *     not a segment but is covered by the windows); Nm = n-m+1 windows.
+ *   - k: order statistic of eq. 13, 1-based.  k <= 0 selects the paper's
+ *     typical value ceil(0.05*2m) = (m+9)/10.  When 2w <= k the largest
+ *     element of P_ABBA is taken, as eq. 13 prescribes.
+ *   - Series are float64 in device memory.  Profiles are float32.
+ *   - The caller owns every buffer.  *_dev arguments are device pointers on the
+ *     context's device; *_host arguments are host pointers.  The library never
+ *     keeps a pointer past return.
+ *   - Work is issued on the stream given to pst_create.  Functions that return
+ *     host results synchronise that stream before returning; the others
+ *     (pst_profile_set, pst_mpdist_profile) also synchronise once, after the
+ *     statistics pass, to report non-finite input.
+ *   - Return value: PST_OK (0) or a negative pst_status.  A message is kept in
+ *     the context (pst_last_error).  After PST_EDEVICE the context is poisoned
+ *     and every later call returns PST_EDEVICE.
+ *   - A context is not thread-safe; use one per host thread.
+ */
+#ifndef PST_H
+#define PST_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PST_OK = 0,
+    PST_EINVAL = -1,     /* bad argument, non-finite series, workspace too small */
+    PST_ENOMEM = -2,     /* does not fit the memory budget */
+    PST_EDEVICE = -3,    /* HIP runtime error; context poisoned */
+    PST_ENOTREADY = -4,  /* serving: result not ready yet */
+    PST_ECANCELED = -5
+} pst_status;
+
+typedef struct pst_ctx pst_ctx;
+
+/* One snippet (section 3.2): its index (the segment number, eq. 5 and the
+ * definition of a snippet's index), its position in greedy order, its
+ * significance frac (eq. 7), and ProfileArea (eq. 17) after it was picked. */
+typedef struct {
+    int32_t segment;
+    int32_t greedy_rank;
+    double  frac;
+    double  area_after;
+} pst_snippet;
+
+/* Library version string. */
+const char *pst_version(void);
+
+/* Create a context on `device`.  `hip_stream` is a hipStream_t (for example
+ * torch.cuda.current_stream().cuda_stream) or NULL for the null stream. */
+int  pst_create(pst_ctx **out, int device, void *hip_stream);
+void pst_destroy(pst_ctx *ctx);
+const char *pst_last_error(const pst_ctx *ctx);
+
+/* Bytes of device workspace needed by pst_profile_set, pst_mpdist_profile and
+ * pst_snippets for these sizes (0 if the sizes are invalid).  The workspace is
+ * caller-allocated, 256-byte aligned, and may be reused between calls. */
+size_t pst_workspace_bytes(int64_t n, int32_t m, int32_t l, int32_t K);
+
+/* Workspace for pst_select_length: the maximum over the candidate lengths.
+ * l_list NULL means l = m/2 for every m. */
+size_t pst_select_length_workspace_bytes(int64_t n, const int32_t *m_list, int32_t num_m,
+                                         const int32_t *l_list, int32_t K);
+
+/* eq. 14: MPdist profile of a query Q (length m) against every length-m window
+ * of T.  out_dev: float32[n-m+1].  Statistics of Q's l-subsequences are taken
+ * from Q itself.  Errors: PST_EINVAL if l < 2, l > m, m > n, w exceeds the
+ * supported maximum (1025), the workspace is too small, or T or Q holds a
+ * non-finite value. */
+int pst_mpdist_profile(pst_ctx *ctx, const double *T_dev, int64_t n,
+                       const double *Q_dev, int32_t m, int32_t l, int32_t k,
+                       float *out_dev, void *ws_dev, size_t ws_bytes);
+
+/* eq. 15: the profile set D = (D_0 .. D_{nseg-1}), D_s = MPD(S_s, T).
+ * D_dev: float32, row s at D_dev + s*ld, ld >= n-m+1.  dmax_dev (optional,
+ * may be NULL): float32[1], receives max over all entries of D (the
+ * denominator of eq. 18).  Errors as pst_mpdist_profile. */
+int pst_profile_set(pst_ctx *ctx, const double *T_dev, int64_t n, int32_t m, int32_t l,
+                    int32_t k, float *D_dev, int64_t ld, float *dmax_dev,
+                    void *ws_dev, size_t ws_bytes);
+
+/* The problem statement of section 3.2: the K most significant snippets of
+ * length m.  out_host: pst_snippet[K], ordered by frac descending (eq. 8),
+ * equal frac kept in greedy order.  Optional outputs (NULL to skip):
+ *   profiles_dev  float32[K][n-m+1], profile of the snippet picked r-th at row r
+ *   owner_dev     int32[n-m+1], greedy rank of the nearest snippet of each
+ *                 window (the Neighbors sets of eq. 6, ties to the earlier pick)
+ *   dmax_host     float32, max over all entries of D
+ * Errors: as above, plus PST_EINVAL if K < 1 or K > nseg (the paper requires
+ * 1 <= K <= n/m). */
+int pst_snippets(pst_ctx *ctx, const double *T_dev, int64_t n, int32_t m, int32_t l,
+                 int32_t k, int32_t K, pst_snippet *out_host, float *profiles_dev,
+                 int32_t *owner_dev, float *dmax_host, void *ws_dev, size_t ws_bytes);
+
+/* eq. 18 over num_m candidate lengths m_list (l_list NULL: l = m/2; k is the
+ * default of each m).  scores_host: float64[num_m] (may be NULL).  m_best
+ * receives the argmax (ties to the smallest m); out_host / profiles_dev /
+ * owner_dev receive the snippets of m_best as in pst_snippets.  K must be valid
+ * for every candidate. */
+int pst_select_length(pst_ctx *ctx, const double *T_dev, int64_t n,
+                      const int32_t *m_list, int32_t num_m, const int32_t *l_list,
+                      int32_t K, int32_t *m_best, double *scores_host,
+                      pst_snippet *out_host, float *profiles_dev, int32_t *owner_dev,
+                      void *ws_dev, size_t ws_bytes);
+
+/* Instrumentation.  With timing on, the profile kernel launched by each call
+ * (eqs. 9-13, the dominant cost) is bracketed by two HIP events recorded on the
+ * context's stream.  pst_last_profile_ms waits for the second event and
+ * returns the kernel's duration in milliseconds; PST_ENOTREADY if no call has
+ * been timed since timing was switched on. */
+int pst_set_timing(pst_ctx *ctx, int on);
+int pst_last_profile_ms(pst_ctx *ctx, float *ms);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PST_H */

@@ -113,6 +113,18 @@ def mpdist_in_series(x: np.ndarray, seg: int, j: int, m: int, l: int, k: int) ->
     return float(mpd_from_ed(E, k)[0])
 
 
+def mpdist_samples(x: np.ndarray, m: int, l: int, k: int, pairs) -> np.ndarray:
+    """D_s(j) for a list of (s, j) pairs, each computed on its own from the
+    w x w block of ED_matr it depends on (statistics over the whole series)."""
+    Z = znorm_matrix(x, l)
+    w = m - l + 1
+    out = []
+    for s, j in pairs:
+        E = ed_matr(Z[s * m: s * m + w], Z[j: j + w])
+        out.append(mpd_from_ed(E, k)[0])
+    return np.array(out)
+
+
 def profile_set(x: np.ndarray, m: int, l: int, k: int | None = None,
                 segments=None) -> np.ndarray:
     """eq. 15: D = (D_1 .. D_{n/m}), D_s = MPD(S_s, T), shape (nseg, n-m+1)."""

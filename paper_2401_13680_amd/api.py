@@ -1,0 +1,162 @@
+"""Python face of the C ABI, with the same names: mpdist_profile, profile_set,
+snippets, select_length.  Inputs are float64 CUDA (ROCm) tensors; outputs are
+torch tensors on the same device.  Work runs on torch's current stream.
+"""
+from __future__ import annotations
+
+import ctypes
+from ctypes import byref, c_double, c_float, c_int32, c_void_p
+
+import torch
+
+from . import _lib
+from ._lib import PstError, Snippet
+
+
+def _ptr(t):
+    return c_void_p(t.data_ptr()) if t is not None else None
+
+
+class Context:
+    """A library context bound to one device and torch's current stream there,
+    with a cached workspace that grows on demand."""
+
+    def __init__(self, device: int = 0, stream=None):
+        self.L = _lib.load()
+        self.device = device
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.stream = stream
+        h = c_void_p()
+        rc = self.L.pst_create(byref(h), device, c_void_p(stream.cuda_stream))
+        if rc != 0:
+            raise PstError(rc, "pst_create failed")
+        self.h = h
+        self._ws = None
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.pst_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def workspace(self, nbytes: int) -> torch.Tensor:
+        if self._ws is None or self._ws.numel() < nbytes:
+            self._ws = None
+            self._ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=f"cuda:{self.device}")
+        return self._ws
+
+    def check(self, rc):
+        if rc != 0:
+            raise PstError(rc, self.L.pst_last_error(self.h).decode())
+
+
+_default: dict = {}
+
+
+def context(device: int = 0) -> Context:
+    stream = torch.cuda.current_stream(device)
+    key = (device, stream.cuda_stream)
+    if key not in _default:
+        _default[key] = Context(device, stream)
+    return _default[key]
+
+
+def _series(T):
+    if not isinstance(T, torch.Tensor) or not T.is_cuda:
+        raise TypeError("T must be a CUDA tensor (the library has no CPU path)")
+    if T.dtype != torch.float64 or T.dim() != 1 or not T.is_contiguous():
+        raise TypeError("T must be a contiguous 1-D float64 tensor")
+    return T
+
+
+def mpdist_profile(T, Q, l: int, k: int = 0, ctx: Context | None = None):
+    """eq. 14: MPdist profile of Q (length m) against every length-m window of T."""
+    T, Q = _series(T), _series(Q)
+    ctx = ctx or context(T.device.index)
+    n, m = T.numel(), Q.numel()
+    nb = ctx.L.pst_workspace_bytes(n, m, l, 0)
+    if nb == 0:
+        raise PstError(-1, f"invalid sizes n={n} m={m} l={l}")
+    out = torch.empty(n - m + 1, dtype=torch.float32, device=T.device)
+    ws = ctx.workspace(nb)
+    ctx.check(ctx.L.pst_mpdist_profile(ctx.h, _ptr(T), n, _ptr(Q), m, l, k, _ptr(out),
+                                        _ptr(ws), ws.numel()))
+    return out
+
+
+def profile_set(T, m: int, l: int, k: int = 0, ctx: Context | None = None):
+    """eq. 15: all segment profiles D [n//m, n-m+1] (float32) and max(D)."""
+    T = _series(T)
+    ctx = ctx or context(T.device.index)
+    n = T.numel()
+    nb = ctx.L.pst_workspace_bytes(n, m, l, 0)
+    if nb == 0:
+        raise PstError(-1, f"invalid sizes n={n} m={m} l={l}")
+    D = torch.empty((n // m, n - m + 1), dtype=torch.float32, device=T.device)
+    dmax = torch.empty(1, dtype=torch.float32, device=T.device)
+    ws = ctx.workspace(nb)
+    ctx.check(ctx.L.pst_profile_set(ctx.h, _ptr(T), n, m, l, k, _ptr(D), D.stride(0), _ptr(dmax),
+                                     _ptr(ws), ws.numel()))
+    return D, dmax
+
+
+def _records(arr, K):
+    return [dict(segment=int(arr[i].segment), greedy_rank=int(arr[i].greedy_rank),
+                 frac=float(arr[i].frac), area_after=float(arr[i].area_after)) for i in range(K)]
+
+
+def snippets(T, m: int, l: int, K: int, k: int = 0, profiles: bool = False, owner: bool = False,
+             ctx: Context | None = None):
+    """Section 3.2's problem: K snippets ordered by frac (eq. 8)."""
+    T = _series(T)
+    ctx = ctx or context(T.device.index)
+    n = T.numel()
+    nb = ctx.L.pst_workspace_bytes(n, m, l, K)
+    if nb == 0:
+        raise PstError(-1, f"invalid sizes n={n} m={m} l={l} K={K}")
+    Nm = n - m + 1
+    prof = torch.empty((K, Nm), dtype=torch.float32, device=T.device) if profiles else None
+    own = torch.empty(Nm, dtype=torch.int32, device=T.device) if owner else None
+    recs = (Snippet * K)()
+    dmax = c_float()
+    ws = ctx.workspace(nb)
+    ctx.check(ctx.L.pst_snippets(ctx.h, _ptr(T), n, m, l, k, K, recs, _ptr(prof), _ptr(own),
+                                  byref(dmax), _ptr(ws), ws.numel()))
+    return dict(records=_records(recs, K), profiles=prof, owner=own, dmax=float(dmax.value))
+
+
+def select_length(T, m_list, K: int, l_list=None, profiles: bool = False, owner: bool = False,
+                  ctx: Context | None = None):
+    """eq. 18: the best snippet length among m_list and its snippets."""
+    T = _series(T)
+    ctx = ctx or context(T.device.index)
+    n = T.numel()
+    num = len(m_list)
+    ms = (c_int32 * num)(*m_list)
+    ls = (c_int32 * num)(*l_list) if l_list is not None else None
+    nb = ctx.L.pst_select_length_workspace_bytes(n, ms, num, ls, K)
+    if nb == 0:
+        raise PstError(-1, "invalid sizes in the candidate list")
+    scores = (c_double * num)()
+    best = c_int32()
+    recs = (Snippet * K)()
+    ws = ctx.workspace(nb)
+    # the profiles / owner of m_best are only known after the sweep: size for the largest Nm
+    Nm_max = n - min(m_list) + 1
+    prof = torch.empty((K, Nm_max), dtype=torch.float32, device=T.device) if profiles else None
+    own = torch.empty(Nm_max, dtype=torch.int32, device=T.device) if owner else None
+    ctx.check(ctx.L.pst_select_length(ctx.h, _ptr(T), n, ms, num, ls, K, byref(best), scores, recs,
+                                       _ptr(prof), _ptr(own), _ptr(ws), ws.numel()))
+    mb = int(best.value)
+    Nm = n - mb + 1
+    if prof is not None:
+        prof = prof.view(-1)[: K * Nm].view(K, Nm)
+    if own is not None:
+        own = own[:Nm]
+    return dict(m_best=mb, scores=list(scores), records=_records(recs, K), profiles=prof, owner=own)

@@ -1,0 +1,90 @@
+// Internal declarations shared by the host runtime and the device code of the
+// MPdist / snippet library.  Not part of the public ABI (include/pst.h is).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace pst {
+
+// Tile geometry of the profile kernel.
+constexpr int kThreads = 256;          // threads per workgroup (4 wave64)
+constexpr int kTileWindows = 1024;     // windows per tile
+constexpr int kMaxDiagPerThread = 12;  // register-resident diagonals per thread
+constexpr int kMaxDiag = kThreads * kMaxDiagPerThread;
+constexpr int kMaxW = 1025;            // largest supported w = m - l + 1
+constexpr int kRowChunk = 8;           // distance-matrix rows staged in LDS at a time
+constexpr int kBuckets = 64;           // radix-select histogram buckets
+constexpr int kCap = 16;               // radix-select candidate list capacity
+constexpr int kScanBlock = 4096;       // elements per block of the prefix-sum scan
+constexpr int kSumBlock = 8192;        // windows per block of the greedy area sums
+
+// Statistics of the length-l subsequences of one series.  The paper evaluates
+// the distance matrix from dot products, means and standard deviations
+// (section 4.1, eq. 9, after its ref. [7]); means here are of the series
+// centred by its global mean.
+struct Stats {
+    const double *xc;  // series minus its global mean, [len]
+    const double *mu;  // centred mean of each window, [Nl]
+    const float *inv;  // 1 / (sigma * sqrt(l)); 0 for a constant window, [Nl]
+    const float *h;    // 0.5 for a constant window, else 0, [Nl]
+    const float *df;   // (x[j+l] - x[j]) / 2, [Nl]; 0 at the last window
+    const float *dg;   // (x[j+l] - mu[j+1]) + (x[j] - mu[j]), [Nl]; 0 at the last
+};
+
+// Device layout of the statistics of one series of length len.
+struct StatsLayout {
+    int64_t len, Nl;
+    int32_t l, nblk;
+    size_t xc, mu, inv, h, df, dg, pre, blk, part, misc, total;
+};
+StatsLayout stats_layout(int64_t len, int32_t l);
+Stats stats_view(char *base, const StatsLayout &L);
+// misc[0] global mean, misc[1] max |x|, misc[2] 1.0 if any value is not finite.
+inline double *stats_misc(char *base, const StatsLayout &L) { return (double *)(base + L.misc); }
+hipError_t launch_series_stats(const double *x, char *base, const StatsLayout &L, hipStream_t st);
+
+// One profile-kernel problem: `nq` queries (segments of T, or one external
+// query) against all windows of T.
+struct ProfileJob {
+    Stats col;             // statistics of T
+    Stats row;             // statistics of the rows' series (T itself, or the query)
+    int64_t row_stride;    // rows of query s start at s * row_stride of the row series
+    int64_t n, Nl, Nm;
+    int32_t m, l, w, k, nq;
+    float *D;              // out: D[s * ld + j]
+    int64_t ld;
+    float *rw;             // scratch: grid * w * kTileWindows floats
+    unsigned *dmax_bits;   // optional: atomic max of D's bit patterns
+    int32_t grid;          // persistent workgroups
+};
+int32_t profile_grid(int64_t tiles);
+size_t profile_scratch_floats(int32_t grid, int32_t w);
+hipError_t launch_profile(const ProfileJob &job, hipStream_t st);
+size_t profile_lds_bytes(int32_t w);   // dynamic LDS of one profile workgroup
+
+// Greedy snippet search and its by-products, all on device (eqs. 6-8, 16-18).
+struct GreedyJob {
+    const float *D;
+    int64_t ld, Nm;
+    int32_t nseg, K;
+    float *M;             // [Nm] representativeness curve
+    double *part;         // [nseg * nblk] partial areas
+    int32_t nblk;
+    int32_t *pick;        // [K]
+    double *area;         // [K]
+    uint8_t *chosen;      // [nseg]
+    int32_t *count;       // [K] neighbours per snippet
+    int32_t *owner;       // [Nm] or null
+    float *profiles;      // [K * Nm] or null
+    double *crit;         // [nblk2 + 1] criterion partial sums; crit[nblk2] = total
+    int32_t nblk2;
+};
+hipError_t launch_greedy(const GreedyJob &g, hipStream_t st);
+// Fill n 32-bit words with v by a kernel (no memset nodes, so it is safe to
+// capture in a graph).
+hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t st);
+hipError_t launch_owner(const GreedyJob &g, hipStream_t st);
+hipError_t launch_criterion(const GreedyJob &g, hipStream_t st);
+
+}  // namespace pst

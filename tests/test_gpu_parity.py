@@ -1,0 +1,185 @@
+"""GPU parity: the HIP library against the FP64 CPU oracle on seeded inputs.
+
+Tolerance (stated for FP32 profiles against FP64): for every profile entry
+    e = |d_gpu^2 - d_ref^2| / (4 l) <= 1e-4
+(relative to the range [0, 4l] of d^2; equivalent to |delta rho| <= 2e-4), and
+    |d_gpu - d_ref| / d_ref <= 1e-4   wherever d_ref >= 0.1 sqrt(l)
+(a plain relative bound where it is meaningful: near d = 0 the square root
+turns one FP32 rounding of rho into ~sqrt(l * 1e-7)).  Snippet indices,
+greedy order and neighbour counts are compared exactly.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2401_13680_amd import api, synth
+from paper_2401_13680_amd._lib import PstError
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-4
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).cuda()
+
+
+def profile_errors(gpu, ref, l):
+    g = np.asarray(gpu, dtype=np.float64)
+    r = np.asarray(ref, dtype=np.float64)
+    e = np.abs(g * g - r * r) / (4.0 * l)
+    mask = r >= 0.1 * math.sqrt(l)
+    rel = np.abs(g - r)[mask] / r[mask] if mask.any() else np.zeros(1)
+    return float(e.max()), float(rel.max())
+
+
+def assert_profiles_close(gpu, ref, l, what=""):
+    e, rel = profile_errors(gpu, ref, l)
+    print(f"{what}: max e={e:.3g} max rel={rel:.3g}", flush=True)
+    assert e <= TOL, (what, e)
+    assert rel <= TOL, (what, rel)
+
+
+CASES = [
+    # name, series, m, l, k
+    ("four_regimes", lambda: synth.four_regimes(1).x, 100, 50, 10),
+    ("ragged_tiles", lambda: synth.regime_series(3100, 21, len_range=(300, 900)).x, 40, 20, 0),
+    ("l_eq_m", lambda: synth.random_tiny(1500, 3), 30, 30, 3),
+    ("l_eq_2", lambda: synth.random_tiny(1200, 4), 24, 2, 0),
+    ("k_over_2w", lambda: synth.random_tiny(900, 5), 20, 18, 10),
+    ("n_not_multiple", lambda: synth.regime_series(2050, 6, len_range=(200, 600)).x, 64, 32, 0),
+    ("wide_w", lambda: synth.regime_series(3000, 7, len_range=(300, 900)).x, 256, 32, 0),
+    ("random_walk", lambda: np.cumsum(np.random.default_rng(8).normal(size=2500)) + 500.0, 50, 25, 0),
+]
+
+
+@pytest.mark.parametrize("name,gen,m,l,k", CASES, ids=[c[0] for c in CASES])
+def test_profile_set_matches_oracle(name, gen, m, l, k):
+    x = gen()
+    print(f"case {name}: n={len(x)} m={m} l={l} k={k}", flush=True)
+    D, dmax = api.profile_set(dev(x), m, l, k)
+    torch.cuda.synchronize()
+    Dref = oracle.profile_set(x, m, l, k if k > 0 else None)
+    assert tuple(D.shape) == Dref.shape
+    Dg = D.cpu().numpy()
+    assert_profiles_close(Dg, Dref, l, name)
+    assert float(dmax.item()) == float(Dg.max())
+
+
+def test_query_profile_matches_oracle():
+    x = synth.four_regimes(1).x
+    q = synth.random_tiny(100, 12)
+    out = api.mpdist_profile(dev(x), dev(q), 50, 10)
+    ref = oracle.mpd(q, x, 50, 10)
+    assert_profiles_close(out.cpu().numpy(), ref, 50, "query")
+    # a window of T as the query scores zero at its own position
+    out2 = api.mpdist_profile(dev(x), dev(x[700:800]), 50, 10).cpu().numpy()
+    assert out2[700] < math.sqrt(2 * 50 * 8 * 2 ** -23)
+
+
+def test_snippets_four_regimes_match_golden():
+    gold = json.load(open(os.path.join(GOLDEN, "snippets_four_regimes_n2000.json")))
+    x = synth.four_regimes(1).x
+    r = api.snippets(dev(x), gold["m"], gold["l"], gold["K"], gold["k"], profiles=True, owner=True)
+    segs = [rec["segment"] for rec in r["records"]]
+    assert segs == [rec["segment"] for rec in gold["records"]]
+    assert [rec["greedy_rank"] for rec in r["records"]] == [rec["greedy_rank"] for rec in gold["records"]]
+    for a, b in zip(r["records"], gold["records"]):
+        assert a["frac"] == b["frac"]
+        assert abs(a["area_after"] - b["area_after"]) <= 1e-4 * b["area_after"]
+    own = r["owner"].cpu().numpy()
+    counts = [int(np.count_nonzero(own == p)) for p in range(gold["K"])]
+    assert counts == gold["counts"]
+    assert abs(r["dmax"] - gold["dmax"]) <= 1e-4 * gold["dmax"]
+
+
+def test_planted_repeats_bit_identical_and_recovered():
+    m, l = 64, 32
+    x, order = synth.planted_motifs(m, 3, [3, 2, 4], seed=1)
+    D, _ = api.profile_set(dev(x), m, l)
+    Dg = D.cpu().numpy()
+    for s in range(len(order)):
+        for t in range(len(order)):
+            if order[s] == order[t]:
+                assert np.array_equal(Dg[s], Dg[t])            # bitwise identical rows
+                assert Dg[s, t * m] <= math.sqrt(2 * l * 8 * 2 ** -23)
+    r = api.snippets(dev(x), m, l, 3)
+    first = {int(np.flatnonzero(order == mid)[0]) for mid in range(3)}
+    assert {rec["segment"] for rec in r["records"]} == first
+    ref = oracle.snippets(x, m, l, 3)
+    assert [rec["segment"] for rec in r["records"]] == [rec["segment"] for rec in ref["records"]]
+
+
+def test_constant_windows_match_oracle():
+    rng = np.random.default_rng(0)
+    x = np.concatenate([np.full(300, 2.0), rng.normal(size=300), np.full(300, -1.0),
+                        np.sin(np.arange(300) / 7.0)])
+    D, _ = api.profile_set(dev(x), 40, 20)
+    ref = oracle.profile_set(x, 40, 20)
+    assert_profiles_close(D.cpu().numpy(), ref, 20, "constant")
+
+
+def test_select_length_matches_oracle():
+    x = synth.regime_series(4000, 9, len_range=(500, 1500)).x
+    ms = [40, 64, 100]
+    r = api.select_length(dev(x), ms, 3, profiles=True, owner=True)
+    ref = oracle.select_length(x, ms, 3)
+    print("scores gpu", r["scores"], "oracle", ref["scores"], flush=True)
+    for a, b in zip(r["scores"], ref["scores"]):
+        assert abs(a - b) <= 1e-3 * max(1.0, abs(b))
+    assert r["m_best"] == ref["m_best"]
+    best = ms.index(ref["m_best"])
+    assert [rec["segment"] for rec in r["records"]] == \
+        [rec["segment"] for rec in ref["results"][best]["records"]]
+    assert r["profiles"].shape == (3, len(x) - ref["m_best"] + 1)
+
+
+def test_errors_are_reported_and_context_survives():
+    x = synth.four_regimes(1).x
+    with pytest.raises(PstError) as ei:
+        api.snippets(dev(x), 100, 50, 21)
+    assert ei.value.code == -1
+    with pytest.raises(PstError):
+        api.profile_set(dev(x), 100, 101)
+    bad = x.copy()
+    bad[1234] = np.nan
+    with pytest.raises(PstError) as ei:
+        api.profile_set(dev(bad), 100, 50)
+    assert "non-finite" in str(ei.value)
+    D, _ = api.profile_set(dev(x), 100, 50)      # the context still works
+    assert torch.isfinite(D).all()
+
+
+def test_deterministic():
+    x = synth.regime_series(5000, 10, len_range=(500, 1500)).x
+    a, _ = api.profile_set(dev(x), 64, 32)
+    b, _ = api.profile_set(dev(x), 64, 32)
+    assert torch.equal(a, b)
+
+
+def test_full_size_sampled_and_snippets():
+    """The 100k-point, m=256 workload at full size: sampled profile entries
+    against the oracle one by one, and the snippets against the stored oracle
+    result."""
+    gold = json.load(open(os.path.join(GOLDEN, "snippets_regimes5_n100000.json")))
+    x = synth.regime_series(100_000, 2, synth.SHAPES5).x
+    m, l, k, K = gold["m"], gold["l"], gold["k"], gold["K"]
+    D, dmax = api.profile_set(dev(x), m, l, k)
+    rng = np.random.default_rng(0)
+    nseg, Nm = D.shape
+    pairs = [(int(rng.integers(nseg)), int(rng.integers(Nm))) for _ in range(60)]
+    pairs += [(s, s * m) for s in range(0, nseg, 97)] + [(nseg - 1, Nm - 1), (0, 0)]
+    ref = oracle.mpdist_samples(x, m, l, k, pairs)
+    Dg = D.cpu().numpy()
+    got = np.array([Dg[s, j] for s, j in pairs])
+    assert_profiles_close(got, ref, l, "full-size samples")
+    assert abs(float(dmax.item()) - gold["dmax"]) <= 1e-4 * gold["dmax"]
+    r = api.snippets(dev(x), m, l, K, k)
+    assert [rec["segment"] for rec in r["records"]] == [rec["segment"] for rec in gold["records"]]
+    for a, b in zip(r["records"], gold["records"]):
+        assert abs(a["frac"] - b["frac"]) <= 1e-3
