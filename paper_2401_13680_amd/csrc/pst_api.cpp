@@ -76,7 +76,7 @@ int plan(pst_ctx *c, int64_t n, int32_t m, int32_t l, int32_t k, int32_t K, Layo
     L->nseg = (int32_t)nseg;
     L->Nl = n - l + 1;
     L->Nm = n - m + 1;
-    L->ntile = (L->Nm + kTileWindows - 1) / kTileWindows;
+    L->ntile = (L->Nm + profile_tile_windows(w) - 1) / profile_tile_windows(w);
     L->grid = profile_grid(L->ntile * nseg);
     L->nblk = (int32_t)((L->Nm + kSumBlock - 1) / kSumBlock);
     L->nblk2 = (int32_t)std::min<int64_t>(1024, (L->Nm + 255) / 256);

@@ -7,15 +7,9 @@
 
 namespace pst {
 
-// Tile geometry of the profile kernel.
-constexpr int kThreads = 256;          // threads per workgroup (4 wave64)
-constexpr int kTileWindows = 1024;     // windows per tile
-constexpr int kMaxDiagPerThread = 12;  // register-resident diagonals per thread
-constexpr int kMaxDiag = kThreads * kMaxDiagPerThread;
+// Profile kernel geometry (the tile width depends on w: see profile_tile_windows).
+constexpr int kProfileThreads = 512;   // threads per profile workgroup (8 wave64)
 constexpr int kMaxW = 1025;            // largest supported w = m - l + 1
-constexpr int kRowChunk = 8;           // distance-matrix rows staged in LDS at a time
-constexpr int kBuckets = 64;           // radix-select histogram buckets
-constexpr int kCap = 16;               // radix-select candidate list capacity
 constexpr int kScanBlock = 4096;       // elements per block of the prefix-sum scan
 constexpr int kSumBlock = 8192;        // windows per block of the greedy area sums
 
@@ -54,10 +48,11 @@ struct ProfileJob {
     int32_t m, l, w, k, nq;
     float *D;              // out: D[s * ld + j]
     int64_t ld;
-    float *rw;             // scratch: grid * w * kTileWindows floats
+    float *rw;             // scratch: grid * w * profile_tile_windows(w) floats
     unsigned *dmax_bits;   // optional: atomic max of D's bit patterns
     int32_t grid;          // persistent workgroups
 };
+int32_t profile_tile_windows(int32_t w);  // windows per tile
 int32_t profile_grid(int64_t tiles);
 size_t profile_scratch_floats(int32_t grid, int32_t w);
 hipError_t launch_profile(const ProfileJob &job, hipStream_t st);

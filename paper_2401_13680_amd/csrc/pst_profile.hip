@@ -3,30 +3,45 @@
 // For query s (a segment S_s of T, eq. 4, or an external query Q) the kernel
 // evaluates the distance matrix ED_matr (eq. 9) between the query's w = m-l+1
 // length-l subsequences (rows) and the series' length-l subsequences
-// (columns), its column minima allP_BA (eq. 10) and its row minima over a
-// sliding window of w columns allP_AB (eq. 11), and for every length-m window
-// j the k-th smallest element of the concatenation P_ABBA (eqs. 12-13).
+// (columns), its column minima allP_BA (eq. 10), its row minima over a sliding
+// window of w columns allP_AB (eq. 11), and for every length-m window j the
+// k-th smallest element of the concatenation P_ABBA (eqs. 12-13).
 //
-// Work is cut into tiles of (query, 1024 consecutive windows); a tile needs the
-// w x (1024 + w - 1) block of the matrix, which it computes along diagonals:
-//   - the centred covariance of row r and column c is anchored by an FP64 dot
-//     product at the first cell of each diagonal inside the tile, and then
-//     advanced in FP32 with the recurrence
-//         cov(r+1, c+1) = cov(r, c) + df[r]*dg[c] + df[c]*dg[r]
-//     (df, dg from the statistics pass);
-//   - every later step is an order statistic and monotone in the Pearson
-//     correlation rho = cov / (l sigma_r sigma_c), so minima of distances are
-//     computed as maxima of rho, and a distance d = sqrt(2 l (1 - rho)) is
-//     formed only for the selected value.
-// Rows are produced in chunks staged in LDS; column maxima accumulate in LDS;
-// row sliding maxima use a doubling (sparse-table) sweep in LDS and go to a
-// per-workgroup scratch slot; the k-th selection is a per-window MSD radix
-// select on order-preserving 32-bit keys of (1 - rho), with per-thread
-// histograms in LDS.
+// Every later step is an order statistic, monotone in the Pearson correlation
+// rho of the two subsequences, because d = sqrt(2 l (1 - rho)).  The kernel
+// therefore works on y = 1 - rho (d^2 = 2 l y) and forms one distance per
+// window, from the selected y.
+//
+// Work unit: a tile of (query, JT consecutive windows), JT = 31 * (number of
+// selection threads).  The tile is computed in sub-tiles of SBW windows; a
+// sub-tile needs the w x (SBW + w - 1) block of the matrix:
+//   1. FP64 anchors: the centred covariance at the first cell of each diagonal
+//      of the block, by a direct dot product (register-blocked along the row).
+//   2. Rows in chunks of V: each thread owns V adjacent diagonals and advances
+//      them one row at a time with the FP32 centred-covariance recurrence
+//          cov(r+1, c+1) = cov(r, c) + df[r]*dg[c] + df[c]*dg[r];
+//      the statistics of its V columns sit in a register window that slides by
+//      one column per row.  The chunk's y values go to LDS.
+//   3. Column minima of y accumulate in LDS for the whole tile (eq. 10).
+//   4. Sliding row minima of width w (eq. 11), per (row, block of 31 windows):
+//      suffix minima of the block and running minima of the window tails in
+//      registers, whole blocks in between from per-block minima in LDS.  They
+//      go to a per-workgroup scratch slot, block-interleaved so that both the
+//      writes here and the reads below are coalesced.
+//   5. Selection (eqs. 12-13): thread a takes the 31 windows of block a, in
+//      order.  A run starts with an MSD radix select on the bits of y that
+//      brackets the ranks k-8 .. k+8 and sorts the values inside; each next
+//      window makes one pass that counts the values below that bracket and
+//      collects the ones inside it (adjacent windows share all but a few of
+//      their 2w values, so the k-th value rarely leaves the bracket), and
+//      takes the next bracket from the sorted list.  A miss is retried once
+//      with a bracket widened on the missing side, then solved by the radix
+//      select (inside the bracket when only the list overflowed).  The result
+//      is exact either way.
 //
 // Arithmetic of a cell depends only on the query's data, the column and the
-// tile's window offset, never on the query's position: identical segments get
-// bit-identical profiles.
+// window offset inside the tile, never on the query's position, so identical
+// segments get bit-identical profiles.
 #include "pst_internal.h"
 
 #include <math.h>
@@ -34,51 +49,174 @@
 namespace pst {
 namespace {
 
-constexpr int NT = kThreads;
-constexpr int JT = kTileWindows;
+constexpr int NT = kProfileThreads;
+constexpr int G = 31;      // windows per block (odd: conflict-free LDS strides)
+constexpr int CAP = 28;    // sorted candidate list capacity
+constexpr int NB = 16;     // radix buckets per level
+constexpr int BAND = 8;    // bracket half-width in ranks
 
-__device__ __forceinline__ uint32_t sel_key(float rho) {
-    float y = 1.0f - rho;
-    y = fminf(fmaxf(y, 0.0f), 2.0f);
-    return __float_as_uint(y);
-}
-
-// Level-0 bucket: 2 buckets per binade of y = 1 - rho, y in [2^-31, 2];
-// smaller values share bucket 0, [1.5, 2] is bucket 63.
-__device__ __forceinline__ int bucket0(uint32_t key) {
-    int b = (int)(key >> 22) - 192;
-    return min(max(b, 0), kBuckets - 1);
-}
+struct Geo {
+    int JT;     // windows per tile
+    int nA;     // selection threads = blocks per tile = JT / G
+    int SBW;    // windows per sub-tile (multiple of G)
+    int V;      // diagonals per thread
+};
 
 struct ProfileArgs {
     ProfileJob J;
-    int32_t rc;       // rows per LDS chunk
-    int32_t cwmax;    // JT + w - 1
+    Geo g;
     float two_l;
 };
 
+__device__ __forceinline__ uint32_t ykey(float y) { return __float_as_uint(fmaxf(y, 0.0f)); }
+
+// In-place insertion sort of the n values L[0], L[NT], ... (per-thread list).
+__device__ __forceinline__ void sort_list(float *L, int n) {
+    for (int x = 1; x < n; ++x) {
+        const float key = L[x * NT];
+        int j = x - 1;
+        while (j >= 0 && L[j * NT] > key) {
+            L[(j + 1) * NT] = L[j * NT];
+            --j;
+        }
+        L[(j + 1) * NT] = key;
+    }
+}
+
+// Values of one window: A(i) for i < w (row minima) and B(c) for c < w
+// (column minima).  each() visits every value exactly once.
+struct Window {
+    const float *rw;   // scratch slot
+    int aoff, astr;    // A(i) = rw[aoff + i * astr]
+    const float *bv;   // B(c) = bv[c]
+    int w;
+    template <typename F>
+    __device__ __forceinline__ void each(F f) const {
+        int i = 0;
+        for (; i + 16 <= w; i += 16) {
+            float y[16];
+#pragma unroll
+            for (int e = 0; e < 16; ++e) y[e] = rw[aoff + (i + e) * astr];
+#pragma unroll
+            for (int e = 0; e < 16; ++e) f(y[e]);
+        }
+        for (; i < w; ++i) f(rw[aoff + i * astr]);
+        for (int c = 0; c < w; ++c) f(bv[c]);
+    }
+};
+
+// Exact radix select of the key range holding ranks r1 .. r2 (1-based) of the
+// window's 2w values.  On return the values of that range are sorted in L,
+// *below counts the values under it, and the k-th smallest is L[k - *below - 1].
+// If the bracket cannot be narrowed to CAP values it falls back to ranks k .. k.
+// A search may start from a key range [lo, hi) already known to hold ranks
+// r1 .. r2 with `base` values below it (shift >= 0), or from scratch (lo = 0,
+// hi = +inf, base = 0, shift = -1: binades of y as the first buckets).
+__device__ int radix_band(const Window &W, int k, int r1, int r2, unsigned *H, float *L, int *below,
+                          uint32_t lo = 0u, uint32_t hi = 0x7F800000u, int base = 0, int shift = -1) {
+    if (shift >= 0) {
+        const uint32_t span = hi - lo;
+        shift = span <= 1u ? 0 : max(0, (32 - __clz((int)(span - 1u))) - 4);
+    }
+    for (int level = 0; level < 16; ++level) {
+#pragma unroll
+        for (int b = 0; b < NB; ++b) H[b * NT] = 0u;
+        W.each([&](float y) {
+            const uint32_t key = ykey(y);
+            if (key >= lo && key < hi) {
+                int b;
+                if (shift < 0) b = min(max(((int)(key >> 23) - 96) >> 1, 0), NB - 1);
+                else b = (int)((key - lo) >> shift);
+                atomicAdd(&H[b * NT], 1u);
+            }
+        });
+        int acc = base, b1 = -1, b2 = NB - 1, below1 = base;
+        for (int b = 0; b < NB; ++b) {
+            const int cb = (int)H[b * NT];
+            if (b1 < 0 && acc + cb >= r1) {
+                b1 = b;
+                below1 = acc;
+            }
+            if (acc + cb >= r2) {
+                b2 = b;
+                acc += cb;
+                break;
+            }
+            acc += cb;
+        }
+        if (b1 < 0) b1 = b2;
+        const int cnt = acc - below1;  // values in buckets b1 .. b2
+        uint32_t nlo, nhi;
+        if (shift < 0) {
+            nlo = b1 == 0 ? 0u : (uint32_t)(2 * b1 + 96) << 23;
+            nhi = b2 == NB - 1 ? 0x7F800000u : (uint32_t)(2 * b2 + 98) << 23;
+        } else {
+            nlo = lo + ((uint32_t)b1 << shift);
+            const uint64_t e = (uint64_t)lo + ((uint64_t)(b2 + 1) << shift);
+            nhi = (uint32_t)(e < (uint64_t)hi ? e : (uint64_t)hi);
+        }
+        const bool stuck = (nlo == lo && nhi == hi);
+        lo = nlo;
+        hi = nhi;
+        base = below1;
+        if (hi - lo == 1u) {  // one key value holds ranks r1 .. r2
+            L[0] = __uint_as_float(lo);
+            *below = base;
+            return 1;
+        }
+        if (cnt <= CAP) {
+            int nc = 0;
+            W.each([&](float y) {
+                const uint32_t key = ykey(y);
+                if (key >= lo && key < hi) L[(nc++) * NT] = __uint_as_float(key);
+            });
+            sort_list(L, nc);
+            *below = base;
+            return nc;
+        }
+        if (stuck) {  // the band spans the whole range: narrow to rank k alone
+            r1 = k;
+            r2 = k;
+        }
+        const uint32_t span = hi - lo;
+        const int lg = 32 - __clz((int)(span - 1u));
+        shift = max(0, lg - 4);
+    }
+    *below = base;  // not reached for finite keys
+    L[0] = __uint_as_float(lo);
+    return 1;
+}
+
+template <int V>
 __global__ void __launch_bounds__(NT) k_profile(ProfileArgs A) {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
+    extern __shared__ __align__(16) float sm[];
     const ProfileJob &J = A.J;
-    const int w = J.w, l = J.l, RC = A.rc, CWM = A.cwmax;
+    const Geo g = A.g;
+    const int w = J.w, l = J.l, JT = g.JT, nA = g.nA, SBW = g.SBW;
     const int t = threadIdx.x;
     const int64_t ntile = (J.Nm + JT - 1) / JT;
     const int64_t total = ntile * (int64_t)J.nq;
     const int keff = min(J.k, 2 * w);
+    const int w4 = (w + 3) & ~3;
+    const int CWT = JT + w - 1;          // columns of a tile
+    const int CWS = SBW + w - 1;         // columns of a sub-tile
 
-    float *c_inv = (float *)smem_raw;
-    float *c_h = c_inv + CWM;
-    float *c_df = c_h + CWM;
-    float *c_dg = c_df + CWM;
-    float *colmax = c_dg + CWM;
-    float *r_inv = colmax + CWM;
-    float *r_h = r_inv + w;
-    float *r_df = r_h + w;
-    float *r_dg = r_df + w;
-    float *buf0 = r_dg + w;
-    float *buf1 = buf0 + RC * CWM;
-    unsigned *hist = (unsigned *)buf0;       // reused after the rows are done
-    unsigned *list = hist + kBuckets * NT;
+    // LDS: column minima of the tile and row statistics, then a region shared
+    // by the sub-tile distance phase and the selection phase.
+    float *colY = sm;
+    float *r_inv = colY + ((CWT + 3) & ~3);
+    float *r_df = r_inv + w4;
+    float *r_dg = r_df + w4;
+    float *r_h = r_dg + w4;
+    float *Ureg = r_h + w4;
+    float *c_inv = Ureg;
+    float *c_df = c_inv + CWS;
+    float *c_dg = c_df + CWS;
+    float *c_h = c_dg + CWS;
+    float *buf = c_h + CWS;      // V rows x CWS
+    float *BM = buf + V * CWS;   // V rows x blocks
+    unsigned *hist = (unsigned *)Ureg;
+    float *lst = (float *)(hist + NB * NT);
 
     float *rw = J.rw + (size_t)blockIdx.x * (size_t)w * JT;
     float tmax = 0.0f;
@@ -88,179 +226,257 @@ __global__ void __launch_bounds__(NT) k_profile(ProfileArgs A) {
         const int64_t J0 = (tile % ntile) * JT;
         const int JTe = (int)min<int64_t>(JT, J.Nm - J0);
         const int CW = JTe + w - 1;
-        const int ndiag = CW + w - 1;
         const int64_t rb = (int64_t)s * J.row_stride;
 
-        __syncthreads();  // previous tile is done with LDS and its scratch slot
-        for (int u = t; u < CW; u += NT) {
-            const int64_t c = J0 + u;
-            c_inv[u] = J.col.inv[c];
-            c_h[u] = J.col.h[c];
-            c_df[u] = J.col.df[c];
-            c_dg[u] = J.col.dg[c];
-            colmax[u] = -INFINITY;
-        }
+        __syncthreads();  // the previous tile is done with LDS and the scratch slot
+        for (int u = t; u < CW; u += NT) colY[u] = INFINITY;
         for (int i = t; i < w; i += NT) {
             const int64_t r = rb + i;
             r_inv[i] = J.row.inv[r];
-            r_h[i] = J.row.h[r];
             r_df[i] = J.row.df[r];
             r_dg[i] = J.row.dg[r];
+            r_h[i] = J.row.h[r];
         }
 
-        // FP64 anchors: centred covariance at the first cell of each diagonal.
-        float cov[kMaxDiagPerThread];
-#pragma unroll
-        for (int q = 0; q < kMaxDiagPerThread; ++q) {
-            const int d = t + q * NT;
-            cov[q] = 0.0f;
-            if (d < ndiag) {
-                const int i0 = max(0, w - 1 - d);
-                const int u0 = d - (w - 1) + i0;
-                const int64_t r = rb + i0;
-                const int64_t c = J0 + u0;
-                const double *xr = J.row.xc + r;
-                const double *xcp = J.col.xc + c;
-                double acc = 0.0;
-                for (int tt = 0; tt < l; ++tt) acc = fma(xr[tt], xcp[tt], acc);
-                acc -= (double)l * J.row.mu[r] * J.col.mu[c];
-                cov[q] = (float)acc;
+        for (int Js = 0; Js < JTe; Js += SBW) {
+            const int JSe = min(SBW, JTe - Js);   // windows of this sub-tile
+            const int CS = JSe + w - 1;           // its columns
+            const int nbl = (CS + G - 1) / G;
+            const bool last = Js + SBW >= JTe;
+            const int own = last ? CS : SBW;      // columns whose minima it owns
+            const int64_t C0 = J0 + Js;           // first column (series index)
+            __syncthreads();  // previous sub-tile done with the shared region
+            for (int u = t; u < CS; u += NT) {
+                const int64_t c = C0 + u;
+                c_inv[u] = J.col.inv[c];
+                c_df[u] = J.col.df[c];
+                c_dg[u] = J.col.dg[c];
+                c_h[u] = J.col.h[c];
             }
-        }
-        __syncthreads();
 
-        for (int R0 = 0; R0 < w; R0 += RC) {
-            const int nr = min(RC, w - R0);
-            // distance-matrix rows R0 .. R0+nr-1 as correlations
+            // 1. FP64 anchors of this thread's V diagonals d0 .. d0+V-1;
+            //    diagonal d holds the cells (i, u = d - (w-1) + i), 0 <= u < CS.
+            const int d0 = t * V;
+            const int ub0 = d0 - (w - 1);
+            const bool full = (ub0 >= 0) && (d0 + V - 1 <= CS - 1);
+            float cov[V];
+            if (full) {
+                const double *xr = J.row.xc + rb;
+                const double *xcp = J.col.xc + C0 + ub0;
+                double acc[V], xs[V];
 #pragma unroll
-            for (int q = 0; q < kMaxDiagPerThread; ++q) {
-                const int d = t + q * NT;
-                if (d < ndiag) {
-                    const int i0 = max(0, w - 1 - d);
-                    const int iend = min(w, CW + w - 1 - d);
-                    const int ilo = max(R0, i0), ihi = min(R0 + nr, iend);
-                    float cv = cov[q];
-                    for (int i = ilo; i < ihi; ++i) {
-                        const int u = d - (w - 1) + i;
-                        const float rho = fmaf(cv * r_inv[i], c_inv[u], r_h[i] + c_h[u]);
-                        buf0[(i - R0) * CW + u] = rho;
-                        cv = fmaf(r_df[i], c_dg[u], fmaf(c_df[u], r_dg[i], cv));
+                for (int v = 0; v < V; ++v) acc[v] = 0.0;
+#pragma unroll
+                for (int v = 0; v < V - 1; ++v) xs[v] = xcp[v];
+                int tt = 0;
+                for (; tt + V <= l; tt += V) {
+#pragma unroll
+                    for (int kq = 0; kq < V; ++kq) {
+                        xs[(kq + V - 1) % V] = xcp[tt + kq + V - 1];
+                        const double a = xr[tt + kq];
+#pragma unroll
+                        for (int v = 0; v < V; ++v) acc[v] = fma(a, xs[(kq + v) % V], acc[v]);
                     }
-                    cov[q] = cv;
+                }
+                for (; tt < l; ++tt) {
+                    const double a = xr[tt];
+#pragma unroll
+                    for (int v = 0; v < V; ++v) acc[v] = fma(a, xcp[tt + v], acc[v]);
+                }
+                const double mr = (double)l * J.row.mu[rb];
+#pragma unroll
+                for (int v = 0; v < V; ++v) cov[v] = (float)(acc[v] - mr * J.col.mu[C0 + ub0 + v]);
+            } else {
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    const int d = d0 + v;
+                    cov[v] = 0.0f;
+                    if (d < CS + w - 1) {
+                        const int i0 = max(0, w - 1 - d);
+                        const int u0 = d - (w - 1) + i0;
+                        const double *xr = J.row.xc + rb + i0;
+                        const double *xcp = J.col.xc + C0 + u0;
+                        double acc = 0.0;
+                        for (int tt = 0; tt < l; ++tt) acc = fma(xr[tt], xcp[tt], acc);
+                        cov[v] = (float)(acc - (double)l * J.row.mu[rb + i0] * J.col.mu[C0 + u0]);
+                    }
                 }
             }
             __syncthreads();
-            // eq. 10 (as a maximum of rho): column maxima over the rows so far
-            for (int u = t; u < CW; u += NT) {
-                float mx = colmax[u];
-                for (int rr = 0; rr < nr; ++rr) mx = fmaxf(mx, buf0[rr * CW + u]);
-                colmax[u] = mx;
+
+            // register window of column statistics: slot (v + k) % V holds the
+            // column of diagonal v at row phase k
+            float wi[V], wf[V], wg[V], wh[V];
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                const int u = min(max(ub0 + v, 0), CS - 1);
+                wi[v] = c_inv[u];
+                wf[v] = c_df[u];
+                wg[v] = c_dg[u];
+                wh[v] = c_h[u];
             }
-            // eq. 11 (as a maximum of rho): sliding maxima of width w by doubling
-            float *src = buf0, *dst = buf1;
-            int h = 1;
-            while (2 * h <= w) {
-                for (int e = t; e < nr * CW; e += NT) {
-                    const int u = e % CW;
-                    if (u + h < CW) dst[e] = fmaxf(src[e], src[e + h]);
+
+            for (int R0 = 0; R0 < w; R0 += V) {
+                const int nr = min(V, w - R0);
+                // 2. rows R0 .. R0+nr-1 of y = 1 - rho
+#pragma unroll
+                for (int k = 0; k < V; ++k) {
+                    const int i = R0 + k;
+                    if (i < w) {
+                        if (i > 0) {
+                            const int sl = (k + V - 1) % V;
+                            const int u = min(max(ub0 + V - 1 + i, 0), CS - 1);
+                            wi[sl] = c_inv[u];
+                            wf[sl] = c_df[u];
+                            wg[sl] = c_dg[u];
+                            wh[sl] = c_h[u];
+                        }
+                        const float ri = r_inv[i], rf = r_df[i], rg = r_dg[i], rh1 = 1.0f - r_h[i];
+                        float *brow = buf + k * CS;
+                        if (full) {
+#pragma unroll
+                            for (int v = 0; v < V; ++v) {
+                                const int sl = (v + k) % V;
+                                brow[ub0 + v + i] = fmaf(-cov[v] * ri, wi[sl], rh1 - wh[sl]);
+                                cov[v] = fmaf(rf, wg[sl], fmaf(wf[sl], rg, cov[v]));
+                            }
+                        } else {
+#pragma unroll
+                            for (int v = 0; v < V; ++v) {
+                                const int sl = (v + k) % V;
+                                const int u = ub0 + v + i;
+                                if (u >= 0) {
+                                    if (u < CS) brow[u] = fmaf(-cov[v] * ri, wi[sl], rh1 - wh[sl]);
+                                    cov[v] = fmaf(rf, wg[sl], fmaf(wf[sl], rg, cov[v]));
+                                }
+                            }
+                        }
+                    }
                 }
                 __syncthreads();
-                float *tmp = src;
-                src = dst;
-                dst = tmp;
-                h *= 2;
+                // 3. column minima of y (eq. 10) for the columns this sub-tile owns
+                for (int u = t; u < own; u += NT) {
+                    float mn = colY[Js + u];
+                    for (int rr = 0; rr < nr; ++rr) mn = fminf(mn, buf[rr * CS + u]);
+                    colY[Js + u] = mn;
+                }
+                // 4. sliding row minima of width w (eq. 11)
+                const int rr = t / nbl;
+                const int al = t - rr * nbl;   // block inside the sub-tile
+                const bool act = rr < nr;
+                float S[G];
+                if (act) {
+                    const float *src = buf + rr * CS + al * G;
+                    const int lim = CS - al * G;
+#pragma unroll
+                    for (int j = 0; j < G; ++j) S[j] = j < lim ? src[j] : INFINITY;
+#pragma unroll
+                    for (int j = G - 2; j >= 0; --j) S[j] = fminf(S[j], S[j + 1]);
+                    BM[rr * nbl + al] = S[0];
+                }
+                __syncthreads();
+                if (act && al * G < JSe) {
+                    const float *row = buf + rr * CS;
+                    const int a = Js / G + al;                 // block inside the tile
+                    const int obase = (R0 + rr) * G * nA + a;  // + p * nA
+                    const int vend = min(G, JSe - al * G);
+                    if (w <= G) {
+                        for (int p = 0; p < vend; ++p) {
+                            const int v = al * G + p;
+                            float mn = INFINITY;
+                            for (int c = 0; c < w; ++c) mn = fminf(mn, row[v + c]);
+                            rw[obase + p * nA] = mn;
+                        }
+                    } else {
+                        const int q = (w - 1) / G;
+                        const int rp = (w - 1) - q * G;
+                        float base = INFINITY;
+                        for (int b = al + 1; b < al + q; ++b) base = fminf(base, BM[rr * nbl + b]);
+                        const int pb = (al + q) * G;
+                        for (int x = 0; x <= rp; ++x) base = fminf(base, row[pb + x]);
+                        // tail: columns al*G + w - 1 + p for p = 1 .. G-1
+                        const int tb = al * G + w - 1;
+                        float pr = base;
+#pragma unroll
+                        for (int p = 0; p < G; ++p) {
+                            if (p > 0) pr = fminf(pr, row[min(tb + p, CS - 1)]);
+                            if (p < vend) rw[obase + p * nA] = fminf(S[p], pr);
+                        }
+                    }
+                }
+                __syncthreads();
             }
-            const int off = w - h;
-            for (int e = t; e < nr * JTe; e += NT) {
-                const int rr = e / JTe, v = e % JTe;
-                rw[(size_t)(R0 + rr) * JT + v] = fmaxf(src[rr * CW + v], src[rr * CW + v + off]);
-            }
-            __syncthreads();
         }
 
-        // eqs. 12-13: k-th smallest distance = k-th largest rho of the 2w values
-        unsigned *H = hist + t;
-        unsigned *L = list + t;
-        for (int v = t; v < JTe; v += NT) {
-            const float *rwv = rw + v;
-            const float *cmv = colmax + v;
-            int kk = keff;
-            uint32_t lo = 0u, hi = 0x40000001u, ans = 0u;
-            int shift = -1;
-            for (int level = 0; level < 8; ++level) {
-                for (int b = 0; b < kBuckets; ++b) H[b * NT] = 0u;
-                for (int i = 0; i < w; ++i) {
-                    const uint32_t key = sel_key(rwv[(size_t)i * JT]);
-                    if (key >= lo && key < hi) {
-                        const int b = shift < 0 ? bucket0(key) : (int)((key - lo) >> shift);
-                        H[b * NT] += 1u;
-                    }
-                }
-                for (int c = 0; c < w; ++c) {
-                    const uint32_t key = sel_key(cmv[c]);
-                    if (key >= lo && key < hi) {
-                        const int b = shift < 0 ? bucket0(key) : (int)((key - lo) >> shift);
-                        H[b * NT] += 1u;
-                    }
-                }
-                int acc = 0, bs = kBuckets - 1;
-                unsigned cnt = 0u;
-                for (int b = 0; b < kBuckets; ++b) {
-                    const unsigned cb = H[b * NT];
-                    if (acc + (int)cb >= kk) {
-                        bs = b;
-                        cnt = cb;
+        // 5. selection (eqs. 12-13): k-th smallest y of the w row minima and the
+        //    w column minima of each window; thread a takes block a in order.
+        if (t < nA) {
+            unsigned *H = hist + t;
+            float *L = lst + t;
+            const int r1 = max(1, keff - BAND), r2 = min(2 * w, keff + BAND);
+            bool have = false;
+            float blo = 0.0f, bhi = 0.0f;
+            for (int p = 0; p < G; ++p) {
+                const int v = t * G + p;
+                if (v >= JTe) break;
+                Window W{rw, p * nA + t, G * nA, colY + v, w};
+                float ystar = 0.0f;
+                bool done = false;
+                int rlo_below = -1;            // restricted radix: known count below blo
+                for (int attempt = 0; attempt < 2 && have && !done; ++attempt) {
+                    int below = 0, nl = 0;
+                    const float lo_ = blo, hi_ = bhi;
+                    W.each([&](float y) {
+                        below += y < lo_;
+                        if (y >= lo_ && y <= hi_) {
+                            if (nl < CAP) L[nl * NT] = y;
+                            ++nl;
+                        }
+                    });
+                    const int kk = keff - below;
+                    if (kk >= 1 && kk <= nl && nl <= CAP) {
+                        sort_list(L, nl);
+                        ystar = L[(kk - 1) * NT];
+                        // next bracket: ranks k-BAND .. k+BAND of this window, or
+                        // extrapolated from the list's spacing where it ends early
+                        const int q1 = r1 - below, q2 = r2 - below;
+                        const float l0 = L[0], l1 = L[(nl - 1) * NT];
+                        const float sp = (l1 - l0) / (float)max(nl - 1, 1);
+                        blo = q1 >= 1 ? L[(q1 - 1) * NT] : l0 - 1.5f * (float)(1 - q1) * sp;
+                        bhi = q2 <= nl ? L[(q2 - 1) * NT] : l1 + 1.5f * (float)(q2 - nl) * sp;
+                        done = true;
+                    } else if (nl > CAP && kk >= 1 && kk <= nl) {
+                        rlo_below = below;     // the k-th is inside: search only there
                         break;
-                    }
-                    acc += (int)cb;
-                }
-                kk -= acc;
-                uint32_t nlo, nhi;
-                if (shift < 0) {
-                    nlo = bs == 0 ? 0u : (uint32_t)(bs + 192) << 22;
-                    nhi = bs == kBuckets - 1 ? 0x40000001u : (uint32_t)(bs + 193) << 22;
-                } else {
-                    nlo = lo + ((uint32_t)bs << shift);
-                    const uint64_t e = (uint64_t)nlo + (1ull << shift);
-                    nhi = (uint32_t)(e < (uint64_t)hi ? e : (uint64_t)hi);
-                }
-                lo = nlo;
-                hi = nhi;
-                ans = lo;
-                if (hi - lo == 1u) break;
-                if ((int)cnt <= kCap) {
-                    int nc = 0;
-                    for (int i = 0; i < w; ++i) {
-                        const uint32_t key = sel_key(rwv[(size_t)i * JT]);
-                        if (key >= lo && key < hi) L[(nc++) * NT] = key;
-                    }
-                    for (int c = 0; c < w; ++c) {
-                        const uint32_t key = sel_key(cmv[c]);
-                        if (key >= lo && key < hi) L[(nc++) * NT] = key;
-                    }
-                    for (int a = 0; a < nc; ++a) {
-                        const uint32_t ka = L[a * NT];
-                        int less = 0, leq = 0;
-                        for (int b = 0; b < nc; ++b) {
-                            const uint32_t kb = L[b * NT];
-                            less += kb < ka;
-                            leq += kb <= ka;
-                        }
-                        if (less < kk && kk <= leq) {
-                            ans = ka;
-                            break;
+                    } else {
+                        const float wd = 3.0f * fmaxf(bhi - blo, 1e-6f);
+                        if (kk < 1) {
+                            bhi = blo;
+                            blo = blo - wd;
+                        } else {
+                            blo = bhi;
+                            bhi = bhi + wd;
                         }
                     }
-                    break;
                 }
-                const uint32_t span = hi - lo;
-                const int lg = 32 - __clz((int)(span - 1u));
-                shift = max(0, lg - 6);
+                if (!done) {
+                    int below = 0, nl;
+                    if (rlo_below >= 0 && blo > 0.0f)
+                        nl = radix_band(W, keff, r1, r2, H, L, &below, ykey(blo),
+                                        ykey(bhi) + 1u, rlo_below, 0);
+                    else
+                        nl = radix_band(W, keff, r1, r2, H, L, &below);
+                    const int kk = keff - below;
+                    ystar = L[(min(max(kk, 1), nl) - 1) * NT];
+                    const int q1 = r1 - below, q2 = r2 - below;
+                    blo = L[(min(max(q1, 1), nl) - 1) * NT];
+                    bhi = L[(min(max(q2, 1), nl) - 1) * NT];
+                    have = true;
+                }
+                const float dist = sqrtf(A.two_l * fmaxf(ystar, 0.0f));
+                J.D[(int64_t)s * J.ld + J0 + v] = dist;
+                tmax = fmaxf(tmax, dist);
             }
-            const float y = __uint_as_float(ans);
-            const float dist = sqrtf(A.two_l * y);
-            J.D[(int64_t)s * J.ld + J0 + v] = dist;
-            tmax = fmaxf(tmax, dist);
         }
     }
 
@@ -277,43 +493,68 @@ __global__ void __launch_bounds__(NT) k_profile(ProfileArgs A) {
     }
 }
 
-size_t lds_bytes(int w, int rc) {
-    const size_t cwm = (size_t)JT + w - 1;
-    const size_t fixed = 4 * (5 * cwm + 4 * (size_t)w);
-    const size_t rows = 2 * (size_t)rc * cwm * 4;
-    const size_t sel = (size_t)(kBuckets + kCap) * NT * 4;
-    return fixed + (rows > sel ? rows : sel);
+Geo geo_for(int w) {
+    Geo g;
+    if (w <= 257) {
+        g.nA = 512;
+        g.SBW = 64 * G;
+    } else if (w <= 513) {
+        g.nA = 256;
+        g.SBW = 64 * G;
+    } else {
+        g.nA = 256;
+        g.SBW = 32 * G;
+    }
+    g.JT = g.nA * G;
+    const int ndiag = g.SBW + 2 * w - 2;
+    g.V = ndiag <= 5 * NT ? 5 : 6;
+    return g;
 }
 
-int pick_rc(int w) {
-    for (int rc = kRowChunk; rc > 1; rc >>= 1)
-        if (lds_bytes(w, rc) <= 150 * 1024) return rc;
-    return 1;
+size_t lds_floats(int w, const Geo &g) {
+    const size_t cwt = (((size_t)g.JT + w - 1) + 3) & ~(size_t)3;
+    const size_t cws = (size_t)g.SBW + w - 1;
+    const size_t nbl = (cws + G - 1) / G;
+    const size_t w4 = ((size_t)w + 3) & ~(size_t)3;
+    const size_t dist = 4 * cws + (size_t)g.V * cws + (size_t)g.V * nbl;
+    const size_t sel = (size_t)(NB + CAP) * NT;
+    return cwt + 4 * w4 + (dist > sel ? dist : sel);
 }
 
 }  // namespace
+
+int32_t profile_tile_windows(int32_t w) { return geo_for(w).JT; }
 
 int32_t profile_grid(int64_t tiles) {
     const int64_t slots = 256;  // one workgroup per compute unit
     return (int32_t)(tiles < slots ? (tiles > 0 ? tiles : 1) : slots);
 }
 
-size_t profile_scratch_floats(int32_t grid, int32_t w) { return (size_t)grid * w * JT; }
-
-hipError_t launch_profile(const ProfileJob &job, hipStream_t st) {
-    ProfileArgs a;
-    a.J = job;
-    a.rc = pick_rc(job.w);
-    a.cwmax = JT + job.w - 1;
-    a.two_l = (float)(2.0 * job.l);
-    const size_t lds = lds_bytes(job.w, a.rc);
-    hipError_t e = hipFuncSetAttribute((const void *)k_profile,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_profile, dim3(job.grid), dim3(NT), lds, st, a);
-    return hipGetLastError();
+size_t profile_scratch_floats(int32_t grid, int32_t w) {
+    return (size_t)grid * w * profile_tile_windows(w);
 }
 
-size_t profile_lds_bytes(int32_t w) { return lds_bytes(w, pick_rc(w)); }
+size_t profile_lds_bytes(int32_t w) { return 4 * lds_floats(w, geo_for(w)); }
+
+hipError_t launch_profile(const ProfileJob &job, hipStream_t st) {
+    const Geo g = geo_for(job.w);
+    ProfileArgs a;
+    a.J = job;
+    a.g = g;
+    a.two_l = (float)(2.0 * job.l);
+    const size_t lds = 4 * lds_floats(job.w, g);
+    const int cws = g.SBW + job.w - 1;
+    const int nbl = (cws + G - 1) / G;
+    // every (row, block) item of a row chunk maps to one thread; every
+    // diagonal of a sub-tile to one thread's register block
+    if (job.w > kMaxW || g.V * nbl > NT || g.V * NT < cws + job.w - 1 || lds > 158 * 1024)
+        return hipErrorInvalidValue;
+    const void *fn = g.V == 5 ? (const void *)k_profile<5> : (const void *)k_profile<6>;
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    if (g.V == 5) hipLaunchKernelGGL(k_profile<5>, dim3(job.grid), dim3(NT), lds, st, a);
+    else hipLaunchKernelGGL(k_profile<6>, dim3(job.grid), dim3(NT), lds, st, a);
+    return hipGetLastError();
+}
 
 }  // namespace pst
