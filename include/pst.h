@@ -113,16 +113,40 @@ int pst_snippets(pst_ctx *ctx, const double *T_dev, int64_t n, int32_t m, int32_
                  int32_t k, int32_t K, pst_snippet *out_host, float *profiles_dev,
                  int32_t *owner_dev, float *dmax_host, void *ws_dev, size_t ws_bytes);
 
-/* eq. 18 over num_m candidate lengths m_list (l_list NULL: l = m/2; k is the
- * default of each m).  scores_host: float64[num_m] (may be NULL).  m_best
- * receives the argmax (ties to the smallest m); out_host / profiles_dev /
- * owner_dev receive the snippets of m_best as in pst_snippets.  K must be valid
- * for every candidate. */
+/* eq. 18 over num_m (1..16) candidate lengths m_list (l_list NULL: l = m/2; k
+ * is the default of each m).  scores_host: float64[num_m] (may be NULL).
+ * m_best receives the argmax (ties to the smallest m); out_host /
+ * profiles_dev / owner_dev receive the snippets of m_best as in pst_snippets.
+ * K must be valid for every candidate.  By default every candidate's profiles
+ * run in one persistent launch, captured with the rest of the sweep as one HIP
+ * graph (replayed when the same pointers and sizes come back); see
+ * pst_set_option.  The workspace must hold pst_select_length_workspace_bytes. */
 int pst_select_length(pst_ctx *ctx, const double *T_dev, int64_t n,
                       const int32_t *m_list, int32_t num_m, const int32_t *l_list,
                       int32_t K, int32_t *m_best, double *scores_host,
                       pst_snippet *out_host, float *profiles_dev, int32_t *owner_dev,
                       void *ws_dev, size_t ws_bytes);
+
+/* Options of a context (value semantics in brackets, default first):
+ *   PST_OPT_SWEEP_GRAPH    capture the length sweep as a HIP graph [1, 0]
+ *   PST_OPT_AUTOTUNE       tune the persistent grid and tile scheduling of the
+ *                          sweep's profile launch on first use of a shape
+ *                          bucket [0, 1]; the choice is kept per process and,
+ *                          if the environment variable PST_AUTOTUNE_CACHE names
+ *                          a file, appended there and read back later
+ *   PST_OPT_PROFILE_GRID   persistent workgroups of the sweep launch [0 = 256]
+ *   PST_OPT_DYNAMIC_TILES  hand tiles out from a device counter [1, 0]
+ *   PST_OPT_SWEEP_BATCHED  one launch for all candidates [1]; 0 runs the
+ *                          candidates one after another (the plain path)
+ * None of them changes any result.  Returns PST_EINVAL for an unknown option. */
+enum {
+    PST_OPT_SWEEP_GRAPH = 1,
+    PST_OPT_AUTOTUNE = 2,
+    PST_OPT_PROFILE_GRID = 3,
+    PST_OPT_DYNAMIC_TILES = 4,
+    PST_OPT_SWEEP_BATCHED = 5
+};
+int pst_set_option(pst_ctx *ctx, int option, int64_t value);
 
 /* Instrumentation.  With timing on, the profile kernel launched by each call
  * (eqs. 9-13, the dominant cost) is bracketed by two HIP events recorded on the

@@ -16,6 +16,8 @@ LIB_PATH = os.path.join(HERE, "libpst.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "pst.h")
 
 PST_OK, PST_EINVAL, PST_ENOMEM, PST_EDEVICE, PST_ENOTREADY, PST_ECANCELED = 0, -1, -2, -3, -4, -5
+PST_OPT_SWEEP_GRAPH, PST_OPT_AUTOTUNE, PST_OPT_PROFILE_GRID, PST_OPT_DYNAMIC_TILES, \
+    PST_OPT_SWEEP_BATCHED = 1, 2, 3, 4, 5
 STATUS_NAMES = {0: "PST_OK", -1: "PST_EINVAL", -2: "PST_ENOMEM", -3: "PST_EDEVICE",
                 -4: "PST_ENOTREADY", -5: "PST_ECANCELED"}
 
@@ -66,6 +68,7 @@ def load():
                                       c_int32, POINTER(c_int32), POINTER(c_double),
                                       POINTER(Snippet), P, P, P, c_size_t]),
         "pst_set_timing": (c_int, [P, c_int]),
+        "pst_set_option": (c_int, [P, c_int, c_int64]),
         "pst_last_profile_ms": (c_int, [P, POINTER(c_float)]),
     }
     for name, (res, args) in sig.items():

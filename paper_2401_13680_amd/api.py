@@ -132,10 +132,17 @@ def snippets(T, m: int, l: int, K: int, k: int = 0, profiles: bool = False, owne
 
 
 def select_length(T, m_list, K: int, l_list=None, profiles: bool = False, owner: bool = False,
+                  batched: bool = True, graph: bool = True, autotune: bool = False,
                   ctx: Context | None = None):
-    """eq. 18: the best snippet length among m_list and its snippets."""
+    """eq. 18: the best snippet length among m_list and its snippets.
+
+    batched: all candidates in one persistent launch (else one after another);
+    graph: capture the batched sweep as a HIP graph; autotune: tune its launch."""
     T = _series(T)
     ctx = ctx or context(T.device.index)
+    ctx.check(ctx.L.pst_set_option(ctx.h, _lib.PST_OPT_SWEEP_BATCHED, int(batched)))
+    ctx.check(ctx.L.pst_set_option(ctx.h, _lib.PST_OPT_SWEEP_GRAPH, int(graph)))
+    ctx.check(ctx.L.pst_set_option(ctx.h, _lib.PST_OPT_AUTOTUNE, int(autotune)))
     n = T.numel()
     num = len(m_list)
     ms = (c_int32 * num)(*m_list)

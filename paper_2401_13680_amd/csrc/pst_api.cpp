@@ -4,21 +4,35 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <vector>
 
 #include "../../include/pst.h"
 #include "pst_internal.h"
 
+struct GraphEntry {
+    std::vector<int64_t> key;
+    hipGraphExec_t exec;
+};
+
 struct pst_ctx {
     int device;
     hipStream_t stream;
+    hipStream_t cap;              // private stream for graph capture (lazily created)
     bool poisoned;
     bool timing;
     bool timed;
     hipEvent_t ev0, ev1;
+    // options (pst_set_option)
+    int opt_graph = 1, opt_autotune = 0, opt_grid = 0, opt_dynamic = 1, opt_batched = 1;
+    std::vector<GraphEntry> graphs;
     char err[512];
 };
 
@@ -235,6 +249,292 @@ int collect_records(pst_ctx *c, const Layout &L, char *ws, pst_snippet *out, flo
     return PST_OK;
 }
 
+
+// ---------------------------------------------------------------- length sweep
+// All candidate lengths of eq. 18 in one persistent profile launch, the greedy
+// search / neighbours / criterion of each candidate after it, and a gather of
+// the per-candidate scalars, optionally captured once as a HIP graph.
+
+struct SweepPlan {
+    int nm = 0, K = 0;
+    int32_t wmax = 0, grid = 0;
+    std::vector<Layout> L;        // per candidate: sizes
+    std::vector<int32_t> ls;      // distinct l
+    std::vector<StatsLayout> SL;  // statistics layout per distinct l
+    std::vector<size_t> o_stats;
+    std::vector<int> li;          // candidate -> distinct-l index
+    struct GB {
+        size_t D, M, part, pick, area, chosen, count, crit, dmax;
+    };
+    std::vector<GB> gb;
+    size_t o_rw = 0, o_counter = 0, o_out = 0, total = 0;
+    int out_stride = 0;
+};
+
+constexpr int32_t kSweepMaxGrid = 256;
+
+int plan_sweep(pst_ctx *c, int64_t n, const int32_t *m_list, int32_t nm, const int32_t *l_list,
+               int32_t K, SweepPlan *P) {
+    if (!m_list || nm < 1) return fail(c, PST_EINVAL, "empty candidate list");
+    if (nm > kMaxJobs) return fail(c, PST_EINVAL, "at most %d candidate lengths per sweep", kMaxJobs);
+    if (K < 1) return fail(c, PST_EINVAL, "need K >= 1 (K=%d)", K);
+    P->nm = nm;
+    P->K = K;
+    P->L.resize(nm);
+    P->li.resize(nm);
+    P->gb.resize(nm);
+    for (int i = 0; i < nm; ++i) {
+        const int32_t l = l_list ? l_list[i] : m_list[i] / 2;
+        const int rc = plan(c, n, m_list[i], l, 0, K, &P->L[i]);
+        if (rc) return rc;
+        P->wmax = std::max(P->wmax, P->L[i].w);
+        int j = 0;
+        while (j < (int)P->ls.size() && P->ls[j] != l) ++j;
+        if (j == (int)P->ls.size()) P->ls.push_back(l);
+        P->li[i] = j;
+    }
+    size_t o = 0;
+    for (int32_t l : P->ls) {
+        P->SL.push_back(stats_layout(n, l));
+        P->o_stats.push_back(o);
+        o = al(o + P->SL.back().total);
+    }
+    P->grid = kSweepMaxGrid;
+    P->o_rw = o;
+    o = al(o + sizeof(float) * (size_t)kSweepMaxGrid * P->wmax * profile_tile_windows(P->wmax));
+    P->o_counter = o;
+    o = al(o + 256);
+    for (int i = 0; i < nm; ++i) {
+        const Layout &L = P->L[i];
+        SweepPlan::GB &g = P->gb[i];
+        g.D = o;      o = al(o + sizeof(float) * (size_t)L.nseg * L.Nm);
+        g.M = o;      o = al(o + sizeof(float) * L.Nm);
+        g.part = o;   o = al(o + sizeof(double) * (size_t)L.nseg * L.nblk);
+        g.pick = o;   o = al(o + sizeof(int32_t) * K);
+        g.area = o;   o = al(o + sizeof(double) * K);
+        g.chosen = o; o = al(o + (size_t)L.nseg);
+        g.count = o;  o = al(o + sizeof(int32_t) * K);
+        g.crit = o;   o = al(o + sizeof(double) * (L.nblk2 + 1));
+        g.dmax = o;   o = al(o + 256);
+    }
+    P->out_stride = 3 + 3 * K;
+    P->o_out = o;
+    o = al(o + sizeof(double) * nm * P->out_stride);
+    P->total = o;
+    return PST_OK;
+}
+
+GreedyJob sweep_greedy(const SweepPlan &P, int i, char *ws) {
+    const Layout &L = P.L[i];
+    const SweepPlan::GB &g = P.gb[i];
+    GreedyJob G{};
+    G.D = (const float *)(ws + g.D);
+    G.ld = L.Nm;
+    G.Nm = L.Nm;
+    G.nseg = L.nseg;
+    G.K = P.K;
+    G.M = (float *)(ws + g.M);
+    G.part = (double *)(ws + g.part);
+    G.nblk = L.nblk;
+    G.pick = (int32_t *)(ws + g.pick);
+    G.area = (double *)(ws + g.area);
+    G.chosen = (uint8_t *)(ws + g.chosen);
+    G.count = (int32_t *)(ws + g.count);
+    G.crit = (double *)(ws + g.crit);
+    G.nblk2 = L.nblk2;
+    return G;
+}
+
+int sweep_jobs(const SweepPlan &P, char *ws, int32_t grid, ProfileJob *jobs) {
+    std::vector<int> order(P.nm);
+    for (int i = 0; i < P.nm; ++i) order[i] = i;
+    // widest problems first: their tiles are the longest
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return P.L[a].w > P.L[b].w; });
+    for (int j = 0; j < P.nm; ++j) {
+        const int i = order[j];
+        const Layout &L = P.L[i];
+        ProfileJob J{};
+        J.col = stats_view(ws + P.o_stats[P.li[i]], P.SL[P.li[i]]);
+        J.row = J.col;
+        J.row_stride = L.m;
+        J.n = L.n;
+        J.Nl = L.Nl;
+        J.Nm = L.Nm;
+        J.m = L.m;
+        J.l = L.l;
+        J.w = L.w;
+        J.k = L.k;
+        J.nq = L.nseg;
+        J.D = (float *)(ws + P.gb[i].D);
+        J.ld = L.Nm;
+        J.rw = (float *)(ws + P.o_rw);
+        J.dmax_bits = (unsigned *)(ws + P.gb[i].dmax);
+        J.grid = grid;
+        jobs[j] = J;
+    }
+    return P.nm;
+}
+
+hipError_t enqueue_sweep(const SweepPlan &P, const double *T, char *ws, int32_t grid, bool dynamic,
+                         hipStream_t st) {
+    hipError_t e;
+    for (size_t j = 0; j < P.ls.size(); ++j)
+        if ((e = launch_series_stats(T, ws + P.o_stats[j], P.SL[j], st)) != hipSuccess) return e;
+    for (int i = 0; i < P.nm; ++i)
+        if ((e = launch_fill_u32((uint32_t *)(ws + P.gb[i].dmax), 1, 0u, st)) != hipSuccess) return e;
+    uint32_t *counter = (uint32_t *)(ws + P.o_counter);
+    if ((e = launch_fill_u32(counter, 1, 0u, st)) != hipSuccess) return e;
+    ProfileJob jobs[kMaxJobs];
+    const int nj = sweep_jobs(P, ws, grid, jobs);
+    if ((e = launch_profile_batch(jobs, nj, grid, dynamic ? counter : nullptr, st)) != hipSuccess) return e;
+    SweepGather Gt{};
+    Gt.nm = P.nm;
+    Gt.K = P.K;
+    Gt.out = (double *)(ws + P.o_out);
+    for (int i = 0; i < P.nm; ++i) {
+        const GreedyJob G = sweep_greedy(P, i, ws);
+        if ((e = launch_greedy(G, st)) != hipSuccess) return e;
+        if ((e = launch_owner(G, st)) != hipSuccess) return e;
+        if ((e = launch_criterion(G, st)) != hipSuccess) return e;
+        Gt.crit[i] = G.crit + G.nblk2;
+        Gt.dmax[i] = (const uint32_t *)(ws + P.gb[i].dmax);
+        Gt.bad[i] = stats_misc(ws + P.o_stats[P.li[i]], P.SL[P.li[i]]) + 2;
+        Gt.area[i] = G.area;
+        Gt.pick[i] = G.pick;
+        Gt.count[i] = G.count;
+    }
+    return launch_gather(Gt, st);
+}
+
+// ---- autotuner: persistent grid size and tile scheduling of the batched
+// profile launch, timed on the caller's own problem the first time a shape
+// bucket is seen; remembered per process and optionally in a text file named
+// by PST_AUTOTUNE_CACHE ("arch wmax tiles_log2 grid dynamic ms" per line).
+// The choice only moves tiles between workgroups: results are identical.
+using TuneKey = std::tuple<std::string, int, int>;
+struct TuneVal {
+    int grid, dynamic;
+    float ms;
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, TuneVal> g_tuned;
+bool g_tune_loaded = false;
+
+void tune_load_locked() {
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char *path = std::getenv("PST_AUTOTUNE_CACHE");
+    if (!path) return;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return;
+    char arch[64];
+    int wm, tl, gr, dy;
+    float ms;
+    while (std::fscanf(f, "%63s %d %d %d %d %f", arch, &wm, &tl, &gr, &dy, &ms) == 6)
+        g_tuned[TuneKey(arch, wm, tl)] = TuneVal{gr, dy, ms};
+    std::fclose(f);
+}
+
+int64_t sweep_tiles(const SweepPlan &P) {
+    const int JT = profile_tile_windows(P.wmax);
+    int64_t t = 0;
+    for (const Layout &L : P.L) t += ((L.Nm + JT - 1) / JT) * (int64_t)L.nseg;
+    return t;
+}
+
+int autotune(pst_ctx *c, const SweepPlan &P, const double *T, char *ws, TuneVal *out) {
+    hipDeviceProp_t prop;
+    HIPCHK(c, hipGetDeviceProperties(&prop, c->device));
+    const int64_t tiles = sweep_tiles(P);
+    const int tl = tiles > 1 ? (int)std::floor(std::log2((double)tiles)) : 0;
+    const TuneKey key(std::string(prop.gcnArchName).substr(0, 6), P.wmax, tl);
+    {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        tune_load_locked();
+        auto it = g_tuned.find(key);
+        if (it != g_tuned.end()) {
+            *out = it->second;
+            return PST_OK;
+        }
+    }
+    // statistics once, then each candidate configuration of the profile launch
+    for (size_t j = 0; j < P.ls.size(); ++j)
+        HIPCHK(c, launch_series_stats(T, ws + P.o_stats[j], P.SL[j], c->stream));
+    const int cand[][2] = {{256, 1}, {256, 0}, {192, 1}, {128, 1}};
+    hipEvent_t a, b;
+    HIPCHK(c, hipEventCreate(&a));
+    HIPCHK(c, hipEventCreate(&b));
+    TuneVal best{256, 1, 1e30f};
+    for (const auto &cf : cand) {
+        ProfileJob jobs[kMaxJobs];
+        const int nj = sweep_jobs(P, ws, cf[0], jobs);
+        uint32_t *counter = (uint32_t *)(ws + P.o_counter);
+        HIPCHK(c, launch_fill_u32(counter, 1, 0u, c->stream));
+        HIPCHK(c, hipEventRecord(a, c->stream));
+        HIPCHK(c, launch_profile_batch(jobs, nj, cf[0], cf[1] ? counter : nullptr, c->stream));
+        HIPCHK(c, hipEventRecord(b, c->stream));
+        HIPCHK(c, hipEventSynchronize(b));
+        float ms = 0.0f;
+        HIPCHK(c, hipEventElapsedTime(&ms, a, b));
+        if (ms < best.ms) best = TuneVal{cf[0], cf[1], ms};
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    g_tuned[key] = best;
+    if (const char *path = std::getenv("PST_AUTOTUNE_CACHE")) {
+        if (FILE *f = std::fopen(path, "a")) {
+            std::fprintf(f, "%s %d %d %d %d %.4f\n", std::get<0>(key).c_str(), P.wmax, tl, best.grid,
+                         best.dynamic, best.ms);
+            std::fclose(f);
+        }
+    }
+    *out = best;
+    return PST_OK;
+}
+
+int run_sweep(pst_ctx *c, const SweepPlan &P, const double *T, char *ws, size_t ws_bytes,
+              const int32_t *m_list, const int32_t *l_list, std::vector<double> *res) {
+    TuneVal cfg{c->opt_grid > 0 ? std::min(c->opt_grid, kSweepMaxGrid) : kSweepMaxGrid, c->opt_dynamic, 0.0f};
+    if (c->opt_autotune) {
+        const int rc = autotune(c, P, T, ws, &cfg);
+        if (rc) return rc;
+    }
+    HIPCHK(c, profile_prepare(P.wmax));
+    if (!c->opt_graph) {
+        HIPCHK(c, enqueue_sweep(P, T, ws, cfg.grid, cfg.dynamic != 0, c->stream));
+    } else {
+        std::vector<int64_t> key = {(int64_t)(uintptr_t)T, P.L[0].n, (int64_t)(uintptr_t)ws,
+                                    (int64_t)ws_bytes, P.nm, P.K, cfg.grid, cfg.dynamic};
+        for (int i = 0; i < P.nm; ++i) {
+            key.push_back(m_list[i]);
+            key.push_back(l_list ? l_list[i] : m_list[i] / 2);
+        }
+        hipGraphExec_t exec = nullptr;
+        for (const GraphEntry &g : c->graphs)
+            if (g.key == key) exec = g.exec;
+        if (!exec) {
+            if (!c->cap) HIPCHK(c, hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
+            HIPCHK(c, hipStreamBeginCapture(c->cap, hipStreamCaptureModeRelaxed));
+            const hipError_t eq = enqueue_sweep(P, T, ws, cfg.grid, cfg.dynamic != 0, c->cap);
+            hipGraph_t graph = nullptr;
+            const hipError_t ee = hipStreamEndCapture(c->cap, &graph);
+            HIPCHK(c, eq);
+            HIPCHK(c, ee);
+            const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            HIPCHK(c, ei);
+            c->graphs.push_back(GraphEntry{key, exec});
+        }
+        HIPCHK(c, hipGraphLaunch(exec, c->stream));
+    }
+    res->assign((size_t)P.nm * P.out_stride, 0.0);
+    HIPCHK(c, hipMemcpyAsync(res->data(), ws + P.o_out, sizeof(double) * res->size(),
+                             hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return PST_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -253,6 +553,7 @@ int pst_create(pst_ctx **out, int device, void *hip_stream) {
     c->timing = false;
     c->timed = false;
     c->ev0 = c->ev1 = nullptr;
+    c->cap = nullptr;
     c->err[0] = 0;
     *out = c;
     return PST_OK;
@@ -260,6 +561,8 @@ int pst_create(pst_ctx **out, int device, void *hip_stream) {
 
 void pst_destroy(pst_ctx *ctx) {
     if (!ctx) return;
+    for (GraphEntry &g : ctx->graphs) (void)hipGraphExecDestroy(g.exec);
+    if (ctx->cap) (void)hipStreamDestroy(ctx->cap);
     if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
     if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
     delete ctx;
@@ -297,15 +600,27 @@ size_t pst_workspace_bytes(int64_t n, int32_t m, int32_t l, int32_t K) {
 
 size_t pst_select_length_workspace_bytes(int64_t n, const int32_t *m_list, int32_t num_m,
                                          const int32_t *l_list, int32_t K) {
-    if (!m_list || num_m < 1) return 0;
-    size_t mx = 0;
-    for (int i = 0; i < num_m; ++i) {
-        const int32_t l = l_list ? l_list[i] : m_list[i] / 2;
-        const size_t b = pst_workspace_bytes(n, m_list[i], l, K);
-        if (b == 0) return 0;
-        mx = std::max(mx, b);
-    }
+    SweepPlan P;
+    if (plan_sweep(nullptr, n, m_list, num_m, l_list, K, &P) != PST_OK) return 0;
+    size_t mx = P.total;  // the per-length path needs at most the largest single layout
+    for (const Layout &L : P.L) mx = std::max(mx, L.total);
     return mx;
+}
+
+int pst_set_option(pst_ctx *ctx, int option, int64_t value) {
+    if (!ctx) return PST_EINVAL;
+    switch (option) {
+        case PST_OPT_SWEEP_GRAPH: ctx->opt_graph = value != 0; break;
+        case PST_OPT_AUTOTUNE: ctx->opt_autotune = value != 0; break;
+        case PST_OPT_PROFILE_GRID:
+            if (value < 0 || value > 4096) return fail(ctx, PST_EINVAL, "grid out of range");
+            ctx->opt_grid = (int)value;
+            break;
+        case PST_OPT_DYNAMIC_TILES: ctx->opt_dynamic = value != 0; break;
+        case PST_OPT_SWEEP_BATCHED: ctx->opt_batched = value != 0; break;
+        default: return fail(ctx, PST_EINVAL, "unknown option %d", option);
+    }
+    return PST_OK;
 }
 
 int pst_mpdist_profile(pst_ctx *ctx, const double *T_dev, int64_t n, const double *Q_dev, int32_t m,
@@ -371,19 +686,60 @@ int pst_select_length(pst_ctx *ctx, const double *T_dev, int64_t n, const int32_
     if (!m_list || num_m < 1 || !m_best || !T_dev)
         return fail(ctx, PST_EINVAL, "need a candidate list, m_best and T");
     if (K < 1) return fail(ctx, PST_EINVAL, "need K >= 1 (K=%d)", K);
-    std::vector<Layout> Ls(num_m);
-    for (int i = 0; i < num_m; ++i) {
-        const int32_t l = l_list ? l_list[i] : m_list[i] / 2;
-        if ((rc = plan(ctx, n, m_list[i], l, 0, K, &Ls[i]))) return rc;
-        if ((rc = check_ws(ctx, Ls[i], ws_dev, ws_bytes))) return rc;
-    }
+    SweepPlan P;
+    if ((rc = plan_sweep(ctx, n, m_list, num_m, l_list, K, &P))) return rc;
     char *ws = (char *)ws_dev;
     int best = -1;
     double best_score = 0.0;
+    if (ctx->opt_batched) {
+        if (!ws) return fail(ctx, PST_EINVAL, "workspace is NULL");
+        if (((uintptr_t)ws & 255) != 0) return fail(ctx, PST_EINVAL, "workspace must be 256-byte aligned");
+        if (ws_bytes < P.total)
+            return fail(ctx, PST_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, P.total);
+        std::vector<double> res;
+        if ((rc = run_sweep(ctx, P, T_dev, ws, ws_bytes, m_list, l_list, &res))) return rc;
+        const int S = P.out_stride;
+        for (int i = 0; i < num_m; ++i)
+            if (res[i * S + 2] != 0.0) return fail(ctx, PST_EINVAL, "T holds a non-finite value");
+        for (int i = 0; i < num_m; ++i) {
+            const uint32_t bits = (uint32_t)res[i * S + 1];
+            float dmax;
+            std::memcpy(&dmax, &bits, sizeof dmax);
+            const double score = dmax > 0.0f ? res[i * S] / (double)dmax : 0.0;
+            if (scores_host) scores_host[i] = score;
+            if (best < 0 || score > best_score || (score == best_score && m_list[i] < m_list[best])) {
+                best = i;
+                best_score = score;
+            }
+        }
+        *m_best = m_list[best];
+        const Layout &L = P.L[best];
+        if (owner_dev || profiles_dev) {
+            GreedyJob G = sweep_greedy(P, best, ws);
+            G.owner = owner_dev;
+            G.profiles = profiles_dev;
+            HIPCHK(ctx, launch_owner(G, ctx->stream));
+            HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+        }
+        std::vector<pst_snippet> rec(K);
+        for (int p = 0; p < K; ++p) {
+            rec[p].segment = (int32_t)res[best * S + 3 + K + p];
+            rec[p].greedy_rank = p;
+            rec[p].frac = res[best * S + 3 + 2 * K + p] / (double)L.Nm;
+            rec[p].area_after = res[best * S + 3 + p];
+        }
+        std::stable_sort(rec.begin(), rec.end(),
+                         [](const pst_snippet &a, const pst_snippet &b) { return a.frac > b.frac; });
+        if (out_host) std::memcpy(out_host, rec.data(), sizeof(pst_snippet) * K);
+        return PST_OK;
+    }
+    // one length at a time (the plain path, kept for comparison)
+    for (int i = 0; i < num_m; ++i)
+        if ((rc = check_ws(ctx, P.L[i], ws_dev, ws_bytes))) return rc;
     for (int i = 0; i < num_m; ++i) {
-        if ((rc = snippets_device(ctx, T_dev, Ls[i], ws, nullptr, nullptr, true))) return rc;
+        if ((rc = snippets_device(ctx, T_dev, P.L[i], ws, nullptr, nullptr, true))) return rc;
         double score = 0.0;
-        if ((rc = collect_records(ctx, Ls[i], ws, nullptr, nullptr, &score))) return rc;
+        if ((rc = collect_records(ctx, P.L[i], ws, nullptr, nullptr, &score))) return rc;
         if (scores_host) scores_host[i] = score;
         if (best < 0 || score > best_score || (score == best_score && m_list[i] < m_list[best])) {
             best = i;
@@ -391,8 +747,8 @@ int pst_select_length(pst_ctx *ctx, const double *T_dev, int64_t n, const int32_
         }
     }
     *m_best = m_list[best];
-    if ((rc = snippets_device(ctx, T_dev, Ls[best], ws, owner_dev, profiles_dev, false))) return rc;
-    return collect_records(ctx, Ls[best], ws, out_host, nullptr, nullptr);
+    if ((rc = snippets_device(ctx, T_dev, P.L[best], ws, owner_dev, profiles_dev, false))) return rc;
+    return collect_records(ctx, P.L[best], ws, out_host, nullptr, nullptr);
 }
 
 }  // extern "C"

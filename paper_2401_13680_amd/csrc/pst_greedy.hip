@@ -160,6 +160,21 @@ __global__ void k_crit_final(GreedyJob g) {
     g.crit[g.nblk2] = 2.0 * s;  // ordered pairs p != q
 }
 
+__global__ void k_gather(SweepGather G) {
+    const int stride = 3 + 3 * G.K;
+    for (int i = threadIdx.x; i < G.nm * stride; i += blockDim.x) {
+        const int c = i / stride, e = i - c * stride;
+        double v;
+        if (e == 0) v = *G.crit[c];
+        else if (e == 1) v = (double)*G.dmax[c];
+        else if (e == 2) v = *G.bad[c];
+        else if (e < 3 + G.K) v = G.area[c][e - 3];
+        else if (e < 3 + 2 * G.K) v = (double)G.pick[c][e - 3 - G.K];
+        else v = (double)G.count[c][e - 3 - 2 * G.K];
+        G.out[i] = v;
+    }
+}
+
 inline int grid_for(int64_t n) {
     int64_t b = (n + GT - 1) / GT;
     return (int)(b < 2048 ? (b > 0 ? b : 1) : 2048);
@@ -187,6 +202,11 @@ hipError_t launch_owner(const GreedyJob &g, hipStream_t st) {
     hipLaunchKernelGGL(k_zero_i32, dim3(grid_for(g.K)), dim3(GT), 0, st, g.count, (int64_t)g.K);
     const size_t lds = g.K <= 1024 ? sizeof(int) * g.K : 0;
     hipLaunchKernelGGL(k_owner, dim3(grid_for(g.Nm)), dim3(GT), lds, st, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather(const SweepGather &g, hipStream_t st) {
+    hipLaunchKernelGGL(k_gather, dim3(1), dim3(256), 0, st, g);
     return hipGetLastError();
 }
 

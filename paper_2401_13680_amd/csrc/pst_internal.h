@@ -52,6 +52,21 @@ struct ProfileJob {
     unsigned *dmax_bits;   // optional: atomic max of D's bit patterns
     int32_t grid;          // persistent workgroups
 };
+// Up to kMaxJobs problems (for example every candidate m of a length sweep)
+// run in one persistent launch; tiles are striped over the workgroups, or
+// handed out by a device counter when `counter` is set (zeroed beforehand).
+constexpr int kMaxJobs = 16;
+struct ProfileBatch {
+    ProfileJob J[kMaxJobs];
+    int64_t tile_end[kMaxJobs];   // job j owns tiles [tile_end[j-1], tile_end[j])
+    int32_t njobs;
+    size_t slot_floats;           // scratch floats per workgroup
+    uint32_t *counter;
+};
+int64_t profile_tiles(const ProfileJob &j);
+hipError_t profile_prepare(int32_t wmax);  // kernel attributes; call outside graph capture
+hipError_t launch_profile_batch(const ProfileJob *jobs, int n, int32_t grid, uint32_t *counter,
+                                hipStream_t st);
 int32_t profile_tile_windows(int32_t w);  // windows per tile
 int32_t profile_grid(int64_t tiles);
 size_t profile_scratch_floats(int32_t grid, int32_t w);
@@ -81,5 +96,20 @@ hipError_t launch_greedy(const GreedyJob &g, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t st);
 hipError_t launch_owner(const GreedyJob &g, hipStream_t st);
 hipError_t launch_criterion(const GreedyJob &g, hipStream_t st);
+
+// Per-candidate results of a length sweep gathered into one device buffer:
+// for candidate i, out[i*(3+3K) ..] = crit total, max D (float bits), the
+// non-finite flag, then K areas, K picks, K neighbour counts (as doubles).
+struct SweepGather {
+    int32_t nm, K;
+    const double *crit[kMaxJobs];
+    const uint32_t *dmax[kMaxJobs];
+    const double *bad[kMaxJobs];
+    const double *area[kMaxJobs];
+    const int32_t *pick[kMaxJobs];
+    const int32_t *count[kMaxJobs];
+    double *out;
+};
+hipError_t launch_gather(const SweepGather &g, hipStream_t st);
 
 }  // namespace pst

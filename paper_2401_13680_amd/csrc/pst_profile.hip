@@ -63,9 +63,8 @@ struct Geo {
 };
 
 struct ProfileArgs {
-    ProfileJob J;
+    ProfileBatch B;
     Geo g;
-    float two_l;
 };
 
 __device__ __forceinline__ uint32_t ykey(float y) { return __float_as_uint(fmaxf(y, 0.0f)); }
@@ -190,38 +189,50 @@ __device__ int radix_band(const Window &W, int k, int r1, int r2, unsigned *H, f
 template <int V>
 __global__ void __launch_bounds__(NT) k_profile(ProfileArgs A) {
     extern __shared__ __align__(16) float sm[];
-    const ProfileJob &J = A.J;
+    __shared__ uint32_t next_tile;
     const Geo g = A.g;
-    const int w = J.w, l = J.l, JT = g.JT, nA = g.nA, SBW = g.SBW;
+    const int JT = g.JT, nA = g.nA, SBW = g.SBW;
     const int t = threadIdx.x;
-    const int64_t ntile = (J.Nm + JT - 1) / JT;
-    const int64_t total = ntile * (int64_t)J.nq;
-    const int keff = min(J.k, 2 * w);
-    const int w4 = (w + 3) & ~3;
-    const int CWT = JT + w - 1;          // columns of a tile
-    const int CWS = SBW + w - 1;         // columns of a sub-tile
+    const int64_t total = A.B.tile_end[A.B.njobs - 1];
+    int64_t gt = blockIdx.x;
+    if (A.B.counter) {  // tiles handed out by a device work counter
+        if (t == 0) next_tile = atomicAdd(A.B.counter, 1u);
+        __syncthreads();
+        gt = next_tile;
+    }
+    while (gt < total) {
+        int jb = 0;
+        while (jb + 1 < A.B.njobs && gt >= A.B.tile_end[jb]) ++jb;
+        const ProfileJob &J = A.B.J[jb];
+        const int64_t tile = gt - (jb > 0 ? A.B.tile_end[jb - 1] : 0);
+        const int w = J.w, l = J.l;
+        const int64_t ntile = (J.Nm + JT - 1) / JT;
+        const int keff = min(J.k, 2 * w);
+        const int w4 = (w + 3) & ~3;
+        const int CWT = JT + w - 1;          // columns of a tile
+        const int CWS = SBW + w - 1;         // columns of a sub-tile
+        const float two_l = (float)(2 * l);
 
-    // LDS: column minima of the tile and row statistics, then a region shared
-    // by the sub-tile distance phase and the selection phase.
-    float *colY = sm;
-    float *r_inv = colY + ((CWT + 3) & ~3);
-    float *r_df = r_inv + w4;
-    float *r_dg = r_df + w4;
-    float *r_h = r_dg + w4;
-    float *Ureg = r_h + w4;
-    float *c_inv = Ureg;
-    float *c_df = c_inv + CWS;
-    float *c_dg = c_df + CWS;
-    float *c_h = c_dg + CWS;
-    float *buf = c_h + CWS;      // V rows x CWS
-    float *BM = buf + V * CWS;   // V rows x blocks
-    unsigned *hist = (unsigned *)Ureg;
-    float *lst = (float *)(hist + NB * NT);
+        // LDS: column minima of the tile and row statistics, then a region
+        // shared by the sub-tile distance phase and the selection phase.
+        float *colY = sm;
+        float *r_inv = colY + ((CWT + 3) & ~3);
+        float *r_df = r_inv + w4;
+        float *r_dg = r_df + w4;
+        float *r_h = r_dg + w4;
+        float *Ureg = r_h + w4;
+        float *c_inv = Ureg;
+        float *c_df = c_inv + CWS;
+        float *c_dg = c_df + CWS;
+        float *c_h = c_dg + CWS;
+        float *buf = c_h + CWS;      // V rows x CWS
+        float *BM = buf + V * CWS;   // V rows x blocks
+        unsigned *hist = (unsigned *)Ureg;
+        float *lst = (float *)(hist + NB * NT);
 
-    float *rw = J.rw + (size_t)blockIdx.x * (size_t)w * JT;
-    float tmax = 0.0f;
+        float *rw = J.rw + (size_t)blockIdx.x * A.B.slot_floats;
+        float tmax = 0.0f;
 
-    for (int64_t tile = blockIdx.x; tile < total; tile += gridDim.x) {
         const int s = (int)(tile / ntile);
         const int64_t J0 = (tile % ntile) * JT;
         const int JTe = (int)min<int64_t>(JT, J.Nm - J0);
@@ -473,23 +484,27 @@ __global__ void __launch_bounds__(NT) k_profile(ProfileArgs A) {
                     bhi = L[(min(max(q2, 1), nl) - 1) * NT];
                     have = true;
                 }
-                const float dist = sqrtf(A.two_l * fmaxf(ystar, 0.0f));
+                const float dist = sqrtf(two_l * fmaxf(ystar, 0.0f));
                 J.D[(int64_t)s * J.ld + J0 + v] = dist;
                 tmax = fmaxf(tmax, dist);
             }
         }
-    }
 
-    if (J.dmax_bits) {
-        __shared__ float red[NT];
-        __syncthreads();
-        red[t] = tmax;
-        __syncthreads();
-        for (int o = NT / 2; o > 0; o >>= 1) {
-            if (t < o) red[t] = fmaxf(red[t], red[t + o]);
-            __syncthreads();
+        // max of D over this tile (the denominator of eq. 18): one atomic per wave
+        if (J.dmax_bits) {
+            float mx = tmax;
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
+            if ((t & 63) == 0) atomicMax(J.dmax_bits, __float_as_uint(mx));
         }
-        if (t == 0) atomicMax(J.dmax_bits, __float_as_uint(red[0]));
+        if (A.B.counter) {
+            __syncthreads();
+            if (t == 0) next_tile = atomicAdd(A.B.counter, 1u);
+            __syncthreads();
+            gt = next_tile;
+        } else {
+            gt += gridDim.x;
+        }
     }
 }
 
@@ -536,25 +551,54 @@ size_t profile_scratch_floats(int32_t grid, int32_t w) {
 
 size_t profile_lds_bytes(int32_t w) { return 4 * lds_floats(w, geo_for(w)); }
 
-hipError_t launch_profile(const ProfileJob &job, hipStream_t st) {
-    const Geo g = geo_for(job.w);
+int64_t profile_tiles(const ProfileJob &j) {
+    const int JT = geo_for(j.w).JT;
+    return ((j.Nm + JT - 1) / JT) * (int64_t)j.nq;
+}
+
+static_assert(sizeof(ProfileArgs) <= 4000, "kernel arguments must fit the 4 KB limit");
+
+hipError_t profile_prepare(int32_t wmax) {
+    const Geo g = geo_for(wmax);
+    const size_t lds = 4 * lds_floats(wmax, g);
+    const void *fn = g.V == 5 ? (const void *)k_profile<5> : (const void *)k_profile<6>;
+    return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+hipError_t launch_profile_batch(const ProfileJob *jobs, int n, int32_t grid, uint32_t *counter,
+                                hipStream_t st) {
+    if (n < 1 || n > kMaxJobs || grid < 1) return hipErrorInvalidValue;
+    int wmax = 0;
+    for (int i = 0; i < n; ++i) wmax = jobs[i].w > wmax ? jobs[i].w : wmax;
+    const Geo g = geo_for(wmax);
     ProfileArgs a;
-    a.J = job;
     a.g = g;
-    a.two_l = (float)(2.0 * job.l);
-    const size_t lds = 4 * lds_floats(job.w, g);
-    const int cws = g.SBW + job.w - 1;
+    a.B.njobs = n;
+    a.B.slot_floats = (size_t)wmax * g.JT;
+    a.B.counter = counter;
+    int64_t acc = 0;
+    for (int i = 0; i < n; ++i) {
+        // all jobs of a batch share the geometry of the widest one
+        a.B.J[i] = jobs[i];
+        acc += ((jobs[i].Nm + g.JT - 1) / g.JT) * (int64_t)jobs[i].nq;
+        a.B.tile_end[i] = acc;
+    }
+    const size_t lds = 4 * lds_floats(wmax, g);
+    const int cws = g.SBW + wmax - 1;
     const int nbl = (cws + G - 1) / G;
     // every (row, block) item of a row chunk maps to one thread; every
     // diagonal of a sub-tile to one thread's register block
-    if (job.w > kMaxW || g.V * nbl > NT || g.V * NT < cws + job.w - 1 || lds > 158 * 1024)
+    if (wmax > kMaxW || g.V * nbl > NT || g.V * NT < cws + wmax - 1 || lds > 158 * 1024)
         return hipErrorInvalidValue;
-    const void *fn = g.V == 5 ? (const void *)k_profile<5> : (const void *)k_profile<6>;
-    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    if (g.V == 5) hipLaunchKernelGGL(k_profile<5>, dim3(job.grid), dim3(NT), lds, st, a);
-    else hipLaunchKernelGGL(k_profile<6>, dim3(job.grid), dim3(NT), lds, st, a);
+    if (g.V == 5) hipLaunchKernelGGL(k_profile<5>, dim3(grid), dim3(NT), lds, st, a);
+    else hipLaunchKernelGGL(k_profile<6>, dim3(grid), dim3(NT), lds, st, a);
     return hipGetLastError();
+}
+
+hipError_t launch_profile(const ProfileJob &job, hipStream_t st) {
+    hipError_t e = profile_prepare(job.w);
+    if (e != hipSuccess) return e;
+    return launch_profile_batch(&job, 1, job.grid, nullptr, st);
 }
 
 }  // namespace pst

@@ -185,3 +185,44 @@ def test_full_size_sampled_and_snippets():
     assert [rec["segment"] for rec in r["records"]] == [rec["segment"] for rec in gold["records"]]
     for a, b in zip(r["records"], gold["records"]):
         assert abs(a["frac"] - b["frac"]) <= 1e-3
+
+
+def _sweep_key(r):
+    return (r["m_best"], list(r["scores"]), [(x["segment"], x["greedy_rank"], x["frac"], x["area_after"])
+                                           for x in r["records"]])
+
+
+def test_sweep_batched_graph_equals_plain_and_oracle():
+    """All candidate lengths in one launch (eager and graph-captured) give the
+    same scores and snippets as the one-length-at-a-time path, bit for bit, and
+    match the oracle."""
+    x = synth.regime_series(6000, 13, len_range=(600, 1500)).x
+    ms = [40, 56, 72, 88]
+    T = dev(x)
+    plain = api.select_length(T, ms, 3, batched=False)
+    eager = api.select_length(T, ms, 3, batched=True, graph=False)
+    assert _sweep_key(eager) == _sweep_key(plain)
+    ref = oracle.select_length(x, ms, 3)
+    for a, b in zip(eager["scores"], ref["scores"]):
+        assert abs(a - b) <= 1e-3 * max(1.0, abs(b))
+    assert eager["m_best"] == ref["m_best"]
+    # graph replays, with eager work and synchronisations in between
+    for rep in range(3):
+        g = api.select_length(T, ms, 3, batched=True, graph=True, profiles=True, owner=True)
+        assert _sweep_key(g) == _sweep_key(eager), rep
+        D, _ = api.profile_set(T, 64, 32)        # unrelated eager work
+        torch.cuda.synchronize()
+    best = ms.index(g["m_best"])
+    Dref = oracle.profile_set(x, g["m_best"], g["m_best"] // 2)
+    picks = [rec["segment"] for rec in sorted(g["records"], key=lambda r: r["greedy_rank"])]
+    assert_profiles_close(g["profiles"].cpu().numpy(), Dref[picks], g["m_best"] // 2, "sweep profiles")
+
+
+def test_sweep_autotune_same_result(tmp_path, monkeypatch):
+    monkeypatch.setenv("PST_AUTOTUNE_CACHE", str(tmp_path / "tune.txt"))
+    x = synth.regime_series(5000, 14, len_range=(500, 1500)).x
+    ms = [48, 64, 80]
+    T = dev(x)
+    a = api.select_length(T, ms, 2, autotune=False)
+    b = api.select_length(T, ms, 2, autotune=True)
+    assert _sweep_key(a) == _sweep_key(b)
