@@ -127,6 +127,45 @@ int pst_select_length(pst_ctx *ctx, const double *T_dev, int64_t n,
                       pst_snippet *out_host, float *profiles_dev, int32_t *owner_dev,
                       void *ws_dev, size_t ws_bytes);
 
+/* ---- Serving ----
+ * A server admits requests (one series each, with its own n, m, l, K) as
+ * device memory and slots free up, runs each admitted request's whole
+ * pipeline (statistics, profiles, greedy search, neighbours) on its own
+ * stream so that requests overlap on the device, and keeps each result until
+ * it is collected.  Admission: first fit in arrival order while the sum of the
+ * admitted requests' footprints (pst_request_bytes) stays within
+ * hbm_budget_bytes and at most max_slots (1..64) run at once.  The server owns
+ * its device memory (cached between requests) and a worker thread.  All
+ * pst_server functions are thread-safe.  A request's result equals that of
+ * pst_snippets on the same input (k is the default of m). */
+typedef struct pst_server pst_server;
+int pst_server_create(pst_server **out, int device, size_t hbm_budget_bytes, int32_t max_slots);
+void pst_server_destroy(pst_server *server);   /* drops requests not yet admitted */
+const char *pst_server_last_error(const pst_server *server);
+/* Device bytes one request holds while admitted (0 if the sizes are invalid). */
+size_t pst_request_bytes(int64_t n, int32_t m, int32_t l, int32_t K);
+/* Queue a request; T_host (n values) is copied before return.  PST_EINVAL for
+ * invalid sizes, PST_ENOMEM if the request can never fit the budget,
+ * PST_EDEVICE after a device error. */
+int pst_submit(pst_server *server, const double *T_host, int64_t n, int32_t m, int32_t l, int32_t K,
+               uint64_t *ticket);
+/* PST_ENOTREADY until the request is done; then fills out_host[K] (ordered
+ * as pst_snippets), the latency from submission to completion in ms, releases
+ * the ticket and returns its status (PST_EINVAL for a non-finite series). */
+int pst_poll(pst_server *server, uint64_t ticket, pst_snippet *out_host, int32_t K, double *latency_ms);
+/* Wait until no request is queued or running: PST_OK, or PST_ENOTREADY at the timeout. */
+int pst_server_drain(pst_server *server, int32_t timeout_ms);
+/* Completed requests, their distance-matrix cells, running requests, bytes held. */
+int pst_server_stats(pst_server *server, uint64_t *completed, double *cells, int32_t *active,
+                     size_t *bytes_in_use);
+/* Host-only simulation of the admission policy (no device use), for tests:
+ * request i of `bytes[i]` arrives at arrive_ms[i] (non-decreasing) and holds
+ * its memory for service_ms[i] after admission; start_ms[i] receives its
+ * admission time, -1 if never admitted.  PST_ENOMEM if some request exceeds
+ * the budget. */
+int pst_admission_simulate(size_t budget, int32_t slots, int32_t count, const size_t *bytes,
+                           const double *arrive_ms, const double *service_ms, double *start_ms);
+
 /* Options of a context (value semantics in brackets, default first):
  *   PST_OPT_SWEEP_GRAPH    capture the length sweep as a HIP graph [1, 0]
  *   PST_OPT_AUTOTUNE       tune the persistent grid and tile scheduling of the

@@ -69,6 +69,17 @@ def load():
                                       POINTER(Snippet), P, P, P, c_size_t]),
         "pst_set_timing": (c_int, [P, c_int]),
         "pst_set_option": (c_int, [P, c_int, c_int64]),
+        "pst_server_create": (c_int, [POINTER(P), c_int, c_size_t, c_int32]),
+        "pst_server_destroy": (None, [P]),
+        "pst_server_last_error": (c_char_p, [P]),
+        "pst_request_bytes": (c_size_t, [c_int64, c_int32, c_int32, c_int32]),
+        "pst_submit": (c_int, [P, P, c_int64, c_int32, c_int32, c_int32, POINTER(ctypes.c_uint64)]),
+        "pst_poll": (c_int, [P, ctypes.c_uint64, POINTER(Snippet), c_int32, POINTER(c_double)]),
+        "pst_server_drain": (c_int, [P, c_int32]),
+        "pst_server_stats": (c_int, [P, POINTER(ctypes.c_uint64), POINTER(c_double), POINTER(c_int32),
+                                     POINTER(c_size_t)]),
+        "pst_admission_simulate": (c_int, [c_size_t, c_int32, c_int32, POINTER(c_size_t),
+                                           POINTER(c_double), POINTER(c_double), POINTER(c_double)]),
         "pst_last_profile_ms": (c_int, [P, POINTER(c_float)]),
     }
     for name, (res, args) in sig.items():

@@ -167,3 +167,64 @@ def select_length(T, m_list, K: int, l_list=None, profiles: bool = False, owner:
     if own is not None:
         own = own[:Nm]
     return dict(m_best=mb, scores=list(scores), records=_records(recs, K), profiles=prof, owner=own)
+
+
+class Server:
+    """Request server of the library (pst_server_*): admission by device-memory
+    footprint and slots, one stream per running request, results kept until
+    polled.  Series are host numpy float64 arrays; each is copied on submit."""
+
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 64 << 30, max_slots: int = 8):
+        self.L = _lib.load()
+        h = c_void_p()
+        rc = self.L.pst_server_create(byref(h), device, hbm_budget_bytes, max_slots)
+        if rc != 0:
+            raise PstError(rc, "pst_server_create failed")
+        self.h = h
+        self.K = {}
+
+    def submit(self, x, m: int, l: int, K: int) -> int:
+        import numpy as np
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        t = ctypes.c_uint64()
+        rc = self.L.pst_submit(self.h, c_void_p(x.ctypes.data), len(x), m, l, K, byref(t))
+        if rc != 0:
+            raise PstError(rc, self.L.pst_server_last_error(self.h).decode())
+        self.K[t.value] = K
+        return t.value
+
+    def poll(self, ticket: int):
+        """None while running; else dict(status, records, latency_ms)."""
+        K = self.K[ticket]
+        recs = (Snippet * K)()
+        lat = c_double()
+        rc = self.L.pst_poll(self.h, ticket, recs, K, byref(lat))
+        if rc == _lib.PST_ENOTREADY:
+            return None
+        del self.K[ticket]
+        return dict(status=rc, records=_records(recs, K) if rc == 0 else None, latency_ms=lat.value)
+
+    def drain(self, timeout_ms: int = 600_000):
+        rc = self.L.pst_server_drain(self.h, timeout_ms)
+        if rc != 0:
+            raise PstError(rc, self.L.pst_server_last_error(self.h).decode())
+
+    def stats(self):
+        c, cells, a, b = ctypes.c_uint64(), c_double(), c_int32(), ctypes.c_size_t()
+        self.L.pst_server_stats(self.h, byref(c), byref(cells), byref(a), byref(b))
+        return dict(completed=c.value, cells=cells.value, active=a.value, bytes_in_use=b.value)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.pst_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def request_bytes(n: int, m: int, l: int, K: int) -> int:
+    return int(_lib.load().pst_request_bytes(n, m, l, K))

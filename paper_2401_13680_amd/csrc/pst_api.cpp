@@ -4,13 +4,18 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <condition_variable>
+#include <deque>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <string>
+#include <thread>
 #include <tuple>
 #include <vector>
 
@@ -752,3 +757,6 @@ int pst_select_length(pst_ctx *ctx, const double *T_dev, int64_t n, const int32_
 }
 
 }  // extern "C"
+
+namespace {
+#include "pst_server.inc"

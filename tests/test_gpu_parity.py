@@ -226,3 +226,28 @@ def test_sweep_autotune_same_result(tmp_path, monkeypatch):
     a = api.select_length(T, ms, 2, autotune=False)
     b = api.select_length(T, ms, 2, autotune=True)
     assert _sweep_key(a) == _sweep_key(b)
+
+
+def test_server_results_equal_alone_and_in_mix():
+    """Requests of different n, m and K submitted together overlap on the
+    device; each result equals the same request run alone with pst_snippets,
+    and a request with a non-finite value fails alone."""
+    specs = [(20_000, 64, 3, 31), (50_000, 256, 4, 32), (8_000, 128, 5, 33),
+             (30_000, 512, 3, 34), (12_000, 96, 4, 35), (40_000, 1024, 3, 36)]
+    xs = [synth.regime_series(n, seed, len_range=(1000, 4000)).x for n, _, _, seed in specs]
+    srv = api.Server(0, hbm_budget_bytes=8 << 30, max_slots=4)
+    tickets = [srv.submit(x, m, m // 2, K) for x, (n, m, K, _) in zip(xs, specs)]
+    bad = xs[2].copy()
+    bad[100] = np.inf
+    tbad = srv.submit(bad, 128, 64, 5)
+    srv.drain()
+    got = [srv.poll(t) for t in tickets]
+    rb = srv.poll(tbad)
+    assert rb["status"] == -1
+    st = srv.stats()
+    srv.close()
+    for g, x, (n, m, K, _) in zip(got, xs, specs):
+        assert g["status"] == 0 and g["latency_ms"] > 0
+        alone = api.snippets(dev(x), m, m // 2, K)
+        assert g["records"] == alone["records"], (n, m, K)
+    assert st["completed"] == len(specs) + 1 and st["active"] == 0
