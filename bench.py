@@ -51,16 +51,112 @@ def cpu_baseline(x, m, l, k, nseg_sample=3):
                        f"{dt:.1f} s), numpy FP64, BLAS limited to 1 thread")
 
 
+def sweep_bench(args):
+    """Length sweep: 250 000-point six-shape series, m in {64, 96, .., 512},
+    l = m/2, K = 6; batched + graph against one length at a time."""
+    import numpy as np
+    import torch
+
+    from paper_2401_13680_amd import api, synth
+
+    n, ms, K = 250_000, list(range(64, 513, 32)), 6
+    x = synth.workload_series("regimes6_n250000_sweep")
+    T = torch.from_numpy(x).cuda()
+    cells = sum((n // m) * (m - m // 2 + 1) * (n - m // 2 + 1) for m in ms)
+    res = {}
+    for mode, kw in (("batched_graph", dict(batched=True, graph=True)), ("plain", dict(batched=False))):
+        for _ in range(args.warmup):
+            api.select_length(T, ms, K, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            r = api.select_length(T, ms, K, **kw)
+        torch.cuda.synchronize()
+        res[mode] = (time.perf_counter() - t0) / args.steps, r["m_best"]
+    dt, mb = res["batched_graph"]
+    out = dict(metric="MPdist distance-matrix cells/sec on 1 MI355X; p50/p99 request latency",
+               value=cells / dt, unit="cells/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
+               ms_per_step=dt * 1e3, higher_is_better=True, scaling="weak", vs_baseline=None,
+               dtype="f32", data="synthetic",
+               config=dict(workload="regimes6_n250000_sweep", n=n, m_list=ms, l="m/2", K=K,
+                           cells_per_step=cells, m_best=mb,
+                           step="all 15 lengths: stats + profiles in one launch + greedy + criterion, one HIP graph"),
+               plain_one_length_at_a_time=dict(value=cells / res["plain"][0], ms_per_step=res["plain"][0] * 1e3),
+               batched_over_plain=res["plain"][0] / dt)
+    print(json.dumps(out), flush=True)
+
+
+def serve_bench(args):
+    """Serving: Poisson arrivals (20 / s) of regime-switching series with n
+    log-uniform in [1e4, 5e5], m in {64, .., 1024}, l = m/2, K in 3..5."""
+    import numpy as np
+    import torch
+
+    from paper_2401_13680_amd import api, synth
+
+    reqs = synth.poisson_requests(num=args.requests, rate=20.0, seed=5)
+    cells = sum((len(r.x) // r.m) * (r.m - r.l + 1) * (len(r.x) - r.l + 1) for r in reqs)
+    # plain: one request after another with pst_snippets
+    Ts = [torch.from_numpy(r.x).cuda() for r in reqs]
+    api.snippets(Ts[0], reqs[0].m, reqs[0].l, reqs[0].K)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for r, T in zip(reqs, Ts):
+        api.snippets(T, r.m, r.l, r.K)
+    torch.cuda.synchronize()
+    plain = time.perf_counter() - t0
+    del Ts
+    srv = api.Server(0, hbm_budget_bytes=96 << 30, max_slots=8)
+    # saturation replay: everything submitted at once
+    t0 = time.perf_counter()
+    tk = [srv.submit(r.x, r.m, r.l, r.K) for r in reqs]
+    srv.drain()
+    sat = time.perf_counter() - t0
+    for t in tk:
+        srv.poll(t)
+    # Poisson replay at the recorded arrival times
+    t0 = time.perf_counter()
+    tickets, lat = [], []
+    for r in reqs:
+        delay = r.arrival_s - (time.perf_counter() - t0)
+        if delay > 0:
+            time.sleep(delay)
+        tickets.append(srv.submit(r.x, r.m, r.l, r.K))
+    srv.drain()
+    span = time.perf_counter() - t0
+    for t in tickets:
+        lat.append(srv.poll(t)["latency_ms"])
+    srv.close()
+    out = dict(metric="MPdist distance-matrix cells/sec on 1 MI355X; p50/p99 request latency",
+               value=cells / sat, unit="cells/s", n_gpus=1, steps=1, warmup=1,
+               ms_per_step=sat * 1e3, higher_is_better=True, scaling="weak", vs_baseline=None,
+               dtype="f32", data="synthetic",
+               config=dict(workload="poisson20_regimes_serving", requests=len(reqs), cells=cells,
+                           step="all requests submitted at once, served with overlap"),
+               latency_ms=dict(p50=float(np.percentile(lat, 50)), p99=float(np.percentile(lat, 99))),
+               poisson_replay=dict(seconds=span, cells_per_s=cells / span),
+               plain_one_request_at_a_time=dict(value=cells / plain, seconds=plain),
+               served_over_plain=plain / sat)
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", default="regimes5_n100000",
+                    choices=["regimes5_n100000", "sweep", "serve"])
+    ap.add_argument("--requests", type=int, default=40, help="serve: number of requests")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py drives exactly one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "sweep":
+        return sweep_bench(args)
+    if args.workload == "serve":
+        return serve_bench(args)
 
     import numpy as np
     import torch

@@ -177,13 +177,20 @@ int pst_admission_simulate(size_t budget, int32_t slots, int32_t count, const si
  *   PST_OPT_DYNAMIC_TILES  hand tiles out from a device counter [1, 0]
  *   PST_OPT_SWEEP_BATCHED  one launch for all candidates [1]; 0 runs the
  *                          candidates one after another (the plain path)
- * None of them changes any result.  Returns PST_EINVAL for an unknown option. */
+ * None of the above changes any result.
+ *   PST_OPT_ANCHOR_EVERY   R > 0: besides the FP64 anchor at the first cell of
+ *                          each diagonal of a sub-tile (at most w-1 FP32 steps
+ *                          apart), re-anchor every diagonal with an exact FP64
+ *                          dot product at rows that are multiples of R [0]
+ *                          (precision study; R >= w-1 changes nothing)
+ * Returns PST_EINVAL for an unknown option. */
 enum {
     PST_OPT_SWEEP_GRAPH = 1,
     PST_OPT_AUTOTUNE = 2,
     PST_OPT_PROFILE_GRID = 3,
     PST_OPT_DYNAMIC_TILES = 4,
-    PST_OPT_SWEEP_BATCHED = 5
+    PST_OPT_SWEEP_BATCHED = 5,
+    PST_OPT_ANCHOR_EVERY = 6
 };
 int pst_set_option(pst_ctx *ctx, int option, int64_t value);
 

@@ -125,6 +125,27 @@ def mpdist_samples(x: np.ndarray, m: int, l: int, k: int, pairs) -> np.ndarray:
     return np.array(out)
 
 
+def mpdist_pairs_local(x: np.ndarray, m: int, l: int, k: int, pairs) -> np.ndarray:
+    """D_s(j) for (s, j) pairs without forming the whole series' z-normalised
+    matrix: each of the 2w subsequences involved is z-normalised on its own
+    (two-pass, population sigma; the constant threshold uses max |T| of the
+    whole series), exactly as znorm_matrix would."""
+    x = np.asarray(x, dtype=np.float64)
+    thr = const_threshold(x)
+    w = m - l + 1
+
+    def z(start):
+        W = sliding(x[start: start + w + l - 1], l)
+        mu = W.mean(axis=1)
+        sig = np.sqrt(((W - mu[:, None]) ** 2).mean(axis=1))
+        c = sig <= thr
+        Z = (W - mu[:, None]) / np.where(c, 1.0, sig)[:, None]
+        Z[c] = 0.0
+        return Z
+
+    return np.array([mpd_from_ed(ed_matr(z(s * m), z(j)), k)[0] for s, j in pairs])
+
+
 def profile_set(x: np.ndarray, m: int, l: int, k: int | None = None,
                 segments=None) -> np.ndarray:
     """eq. 15: D = (D_1 .. D_{n/m}), D_s = MPD(S_s, T), shape (nseg, n-m+1)."""

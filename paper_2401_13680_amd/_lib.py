@@ -17,7 +17,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "pst.h")
 
 PST_OK, PST_EINVAL, PST_ENOMEM, PST_EDEVICE, PST_ENOTREADY, PST_ECANCELED = 0, -1, -2, -3, -4, -5
 PST_OPT_SWEEP_GRAPH, PST_OPT_AUTOTUNE, PST_OPT_PROFILE_GRID, PST_OPT_DYNAMIC_TILES, \
-    PST_OPT_SWEEP_BATCHED = 1, 2, 3, 4, 5
+    PST_OPT_SWEEP_BATCHED, PST_OPT_ANCHOR_EVERY = 1, 2, 3, 4, 5, 6
 STATUS_NAMES = {0: "PST_OK", -1: "PST_EINVAL", -2: "PST_ENOMEM", -3: "PST_EDEVICE",
                 -4: "PST_ENOTREADY", -5: "PST_ECANCELED"}
 

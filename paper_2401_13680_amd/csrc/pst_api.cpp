@@ -36,7 +36,7 @@ struct pst_ctx {
     bool timed;
     hipEvent_t ev0, ev1;
     // options (pst_set_option)
-    int opt_graph = 1, opt_autotune = 0, opt_grid = 0, opt_dynamic = 1, opt_batched = 1;
+    int opt_graph = 1, opt_autotune = 0, opt_grid = 0, opt_dynamic = 1, opt_batched = 1, opt_anchor = 0;
     std::vector<GraphEntry> graphs;
     char err[512];
 };
@@ -145,7 +145,8 @@ int series_stats(pst_ctx *c, const double *x, char *base, const StatsLayout &SL,
 }
 
 // Launch the profile kernel, bracketed by the context's events when timing.
-hipError_t timed_profile(pst_ctx *c, const ProfileJob &j) {
+hipError_t timed_profile(pst_ctx *c, ProfileJob j) {
+    j.anchor_every = c->opt_anchor;
     if (c->timing) {
         hipError_t e = hipEventRecord(c->ev0, c->stream);
         if (e != hipSuccess) return e;
@@ -350,7 +351,7 @@ GreedyJob sweep_greedy(const SweepPlan &P, int i, char *ws) {
     return G;
 }
 
-int sweep_jobs(const SweepPlan &P, char *ws, int32_t grid, ProfileJob *jobs) {
+int sweep_jobs(const SweepPlan &P, char *ws, int32_t grid, ProfileJob *jobs, int32_t anchor = 0) {
     std::vector<int> order(P.nm);
     for (int i = 0; i < P.nm; ++i) order[i] = i;
     // widest problems first: their tiles are the longest
@@ -375,13 +376,14 @@ int sweep_jobs(const SweepPlan &P, char *ws, int32_t grid, ProfileJob *jobs) {
         J.rw = (float *)(ws + P.o_rw);
         J.dmax_bits = (unsigned *)(ws + P.gb[i].dmax);
         J.grid = grid;
+        J.anchor_every = anchor;
         jobs[j] = J;
     }
     return P.nm;
 }
 
 hipError_t enqueue_sweep(const SweepPlan &P, const double *T, char *ws, int32_t grid, bool dynamic,
-                         hipStream_t st) {
+                         hipStream_t st, int32_t anchor) {
     hipError_t e;
     for (size_t j = 0; j < P.ls.size(); ++j)
         if ((e = launch_series_stats(T, ws + P.o_stats[j], P.SL[j], st)) != hipSuccess) return e;
@@ -390,7 +392,7 @@ hipError_t enqueue_sweep(const SweepPlan &P, const double *T, char *ws, int32_t 
     uint32_t *counter = (uint32_t *)(ws + P.o_counter);
     if ((e = launch_fill_u32(counter, 1, 0u, st)) != hipSuccess) return e;
     ProfileJob jobs[kMaxJobs];
-    const int nj = sweep_jobs(P, ws, grid, jobs);
+    const int nj = sweep_jobs(P, ws, grid, jobs, anchor);
     if ((e = launch_profile_batch(jobs, nj, grid, dynamic ? counter : nullptr, st)) != hipSuccess) return e;
     SweepGather Gt{};
     Gt.nm = P.nm;
@@ -507,10 +509,10 @@ int run_sweep(pst_ctx *c, const SweepPlan &P, const double *T, char *ws, size_t 
     }
     HIPCHK(c, profile_prepare(P.wmax));
     if (!c->opt_graph) {
-        HIPCHK(c, enqueue_sweep(P, T, ws, cfg.grid, cfg.dynamic != 0, c->stream));
+        HIPCHK(c, enqueue_sweep(P, T, ws, cfg.grid, cfg.dynamic != 0, c->stream, c->opt_anchor));
     } else {
         std::vector<int64_t> key = {(int64_t)(uintptr_t)T, P.L[0].n, (int64_t)(uintptr_t)ws,
-                                    (int64_t)ws_bytes, P.nm, P.K, cfg.grid, cfg.dynamic};
+                                    (int64_t)ws_bytes, P.nm, P.K, cfg.grid, cfg.dynamic, c->opt_anchor};
         for (int i = 0; i < P.nm; ++i) {
             key.push_back(m_list[i]);
             key.push_back(l_list ? l_list[i] : m_list[i] / 2);
@@ -521,7 +523,7 @@ int run_sweep(pst_ctx *c, const SweepPlan &P, const double *T, char *ws, size_t 
         if (!exec) {
             if (!c->cap) HIPCHK(c, hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
             HIPCHK(c, hipStreamBeginCapture(c->cap, hipStreamCaptureModeRelaxed));
-            const hipError_t eq = enqueue_sweep(P, T, ws, cfg.grid, cfg.dynamic != 0, c->cap);
+            const hipError_t eq = enqueue_sweep(P, T, ws, cfg.grid, cfg.dynamic != 0, c->cap, c->opt_anchor);
             hipGraph_t graph = nullptr;
             const hipError_t ee = hipStreamEndCapture(c->cap, &graph);
             HIPCHK(c, eq);
@@ -623,6 +625,10 @@ int pst_set_option(pst_ctx *ctx, int option, int64_t value) {
             break;
         case PST_OPT_DYNAMIC_TILES: ctx->opt_dynamic = value != 0; break;
         case PST_OPT_SWEEP_BATCHED: ctx->opt_batched = value != 0; break;
+        case PST_OPT_ANCHOR_EVERY:
+            if (value < 0 || value > (1 << 30)) return fail(ctx, PST_EINVAL, "anchor interval out of range");
+            ctx->opt_anchor = (int)value;
+            break;
         default: return fail(ctx, PST_EINVAL, "unknown option %d", option);
     }
     return PST_OK;

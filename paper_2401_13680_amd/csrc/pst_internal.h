@@ -51,6 +51,7 @@ struct ProfileJob {
     float *rw;             // scratch: grid * w * profile_tile_windows(w) floats
     unsigned *dmax_bits;   // optional: atomic max of D's bit patterns
     int32_t grid;          // persistent workgroups
+    int32_t anchor_every;  // > 0: also re-anchor every diagonal at rows i % anchor_every == 0
 };
 // Up to kMaxJobs problems (for example every candidate m of a length sweep)
 // run in one persistent launch; tiles are striped over the workgroups, or

@@ -186,6 +186,16 @@ __device__ int radix_band(const Window &W, int k, int r1, int r2, unsigned *H, f
     return 1;
 }
 
+// Centred covariance of row r = rb + i and column C0 + u by a direct FP64 dot
+// product (the anchor of a diagonal).
+__device__ __noinline__ float anchor_at(const ProfileJob &J, int64_t rb, int i, int64_t C0, int u) {
+    const double *xr = J.row.xc + rb + i;
+    const double *xcp = J.col.xc + C0 + u;
+    double acc = 0.0;
+    for (int tt = 0; tt < J.l; ++tt) acc = fma(xr[tt], xcp[tt], acc);
+    return (float)(acc - (double)J.l * J.row.mu[rb + i] * J.col.mu[C0 + u]);
+}
+
 template <int V>
 __global__ void __launch_bounds__(NT) k_profile(ProfileArgs A) {
     extern __shared__ __align__(16) float sm[];
@@ -341,6 +351,15 @@ __global__ void __launch_bounds__(NT) k_profile(ProfileArgs A) {
                             wf[sl] = c_df[u];
                             wg[sl] = c_dg[u];
                             wh[sl] = c_h[u];
+                        }
+                        if (J.anchor_every > 0 && i > 0 && i % J.anchor_every == 0) {
+                            // optional FP64 re-anchor: the FP32 recurrence never
+                            // runs more than anchor_every steps
+#pragma unroll
+                            for (int v = 0; v < V; ++v) {
+                                const int u = ub0 + v + i;
+                                if (u >= 0 && u < CS) cov[v] = anchor_at(J, rb, i, C0, u);
+                            }
                         }
                         const float ri = r_inv[i], rf = r_df[i], rg = r_dg[i], rh1 = 1.0f - r_h[i];
                         float *brow = buf + k * CS;

@@ -251,3 +251,14 @@ def test_server_results_equal_alone_and_in_mix():
         alone = api.snippets(dev(x), m, m // 2, K)
         assert g["records"] == alone["records"], (n, m, K)
     assert st["completed"] == len(specs) + 1 and st["active"] == 0
+
+
+def test_reanchor_option_keeps_parity():
+    x = synth.regime_series(4000, 19, len_range=(400, 1200)).x
+    ctx = api.context(0)
+    ref = oracle.profile_set(x, 80, 40)
+    for R in (7, 16):
+        ctx.check(ctx.L.pst_set_option(ctx.h, 6, R))
+        D, _ = api.profile_set(dev(x), 80, 40, ctx=ctx)
+        assert_profiles_close(D.cpu().numpy(), ref, 40, f"R={R}")
+    ctx.check(ctx.L.pst_set_option(ctx.h, 6, 0))

@@ -206,3 +206,13 @@ def test_select_length_prefers_distinct_shapes():
 def test_default_k_matches_five_percent_of_2m():
     for m in range(2, 5001):
         assert oracle.default_k(m) == math.ceil(round(0.05 * 2 * m, 9))
+
+
+def test_local_pairs_equal_full_profile():
+    x = synth.regime_series(3000, 17, len_range=(300, 900)).x
+    m, l, k = 60, 30, 6
+    D = oracle.profile_set(x, m, l, k)
+    rng = np.random.default_rng(1)
+    pairs = [(int(rng.integers(D.shape[0])), int(rng.integers(D.shape[1]))) for _ in range(30)]
+    got = oracle.mpdist_pairs_local(x, m, l, k, pairs)
+    np.testing.assert_allclose(got ** 2, [D[s, j] ** 2 for s, j in pairs], atol=1e-9)
