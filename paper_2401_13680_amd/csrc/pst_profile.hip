@@ -34,10 +34,11 @@
 //      window makes one pass that counts the values below that bracket and
 //      collects the ones inside it (adjacent windows share all but a few of
 //      their 2w values, so the k-th value rarely leaves the bracket), and
-//      takes the next bracket from the sorted list.  A miss is retried once
-//      with a bracket widened on the missing side, then solved by the radix
-//      select (inside the bracket when only the list overflowed).  The result
-//      is exact either way.
+//      takes the next bracket from the sorted list.  Windows whose bracket
+//      misses (and the first window of each run) are solved by the 64 lanes of
+//      the wave together, one window at a time, with the radix select, so a
+//      rare miss costs the wave a short cooperative step instead of stalling
+//      every lane.  The result is exact either way.
 //
 // Arithmetic of a cell depends only on the query's data, the column and the
 // window offset inside the tile, never on the query's position, so identical
@@ -100,38 +101,61 @@ struct Window {
             for (int e = 0; e < 16; ++e) f(y[e]);
         }
         for (; i < w; ++i) f(rw[aoff + i * astr]);
-        for (int c = 0; c < w; ++c) f(bv[c]);
+        int c = 0;
+        for (; c + 16 <= w; c += 16) {
+            float y[16];
+#pragma unroll
+            for (int e = 0; e < 16; ++e) y[e] = bv[c + e];
+#pragma unroll
+            for (int e = 0; e < 16; ++e) f(y[e]);
+        }
+        for (; c < w; ++c) f(bv[c]);
     }
 };
 
-// Exact radix select of the key range holding ranks r1 .. r2 (1-based) of the
-// window's 2w values.  On return the values of that range are sorted in L,
-// *below counts the values under it, and the k-th smallest is L[k - *below - 1].
-// If the bracket cannot be narrowed to CAP values it falls back to ranks k .. k.
-// A search may start from a key range [lo, hi) already known to hold ranks
-// r1 .. r2 with `base` values below it (shift >= 0), or from scratch (lo = 0,
-// hi = +inf, base = 0, shift = -1: binades of y as the first buckets).
-__device__ int radix_band(const Window &W, int k, int r1, int r2, unsigned *H, float *L, int *below,
-                          uint32_t lo = 0u, uint32_t hi = 0x7F800000u, int base = 0, int shift = -1) {
-    if (shift >= 0) {
-        const uint32_t span = hi - lo;
-        shift = span <= 1u ? 0 : max(0, (32 - __clz((int)(span - 1u))) - 4);
-    }
+// Orders LDS accesses of the lanes of one wave (they execute in lockstep).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Per-wave LDS scratch of the cooperative select.
+struct Coop {
+    unsigned *hist;   // NB counters
+    unsigned *cnt;    // 1 counter
+    float *list;      // CAP values
+    float *sorted;    // CAP values
+};
+constexpr int COOP_FLOATS = NB + 4 + 2 * CAP;
+
+// Exact radix select, by the 64 lanes of a wave together, of the key range
+// holding ranks r1 .. r2 (1-based) of one window's 2w values: A(i) =
+// rw[aoff + i*astr] for i < w and B(c) = bv[c] for c < w.  Every lane gets
+// *below (values under the range) and the count of values in it; those values
+// are left sorted in C.sorted.  If the range cannot be narrowed to CAP values
+// the ranks shrink to k .. k.  Must be called by all lanes of the wave.
+__device__ __forceinline__ int coop_band(const float *rw, int aoff, int astr, const float *bv, int w, int k, int r1,
+                         int r2, const Coop &C, int lane, int *below) {
+    uint32_t lo = 0u, hi = 0x7F800000u;
+    int base = 0, shift = -1;
     for (int level = 0; level < 16; ++level) {
-#pragma unroll
-        for (int b = 0; b < NB; ++b) H[b * NT] = 0u;
-        W.each([&](float y) {
+        if (lane < NB) C.hist[lane] = 0u;
+        wave_sync();
+        auto add = [&](float y) {
             const uint32_t key = ykey(y);
             if (key >= lo && key < hi) {
                 int b;
                 if (shift < 0) b = min(max(((int)(key >> 23) - 96) >> 1, 0), NB - 1);
                 else b = (int)((key - lo) >> shift);
-                atomicAdd(&H[b * NT], 1u);
+                atomicAdd(&C.hist[b], 1u);
             }
-        });
+        };
+        for (int i = lane; i < w; i += 64) add(rw[aoff + i * astr]);
+        for (int c = lane; c < w; c += 64) add(bv[c]);
+        wave_sync();
         int acc = base, b1 = -1, b2 = NB - 1, below1 = base;
         for (int b = 0; b < NB; ++b) {
-            const int cb = (int)H[b * NT];
+            const int cb = (int)C.hist[b];
             if (b1 < 0 && acc + cb >= r1) {
                 b1 = b;
                 below1 = acc;
@@ -158,20 +182,35 @@ __device__ int radix_band(const Window &W, int k, int r1, int r2, unsigned *H, f
         lo = nlo;
         hi = nhi;
         base = below1;
+        wave_sync();  // every lane has read the histogram
         if (hi - lo == 1u) {  // one key value holds ranks r1 .. r2
-            L[0] = __uint_as_float(lo);
+            if (lane == 0) C.sorted[0] = __uint_as_float(lo);
+            wave_sync();
             *below = base;
             return 1;
         }
         if (cnt <= CAP) {
-            int nc = 0;
-            W.each([&](float y) {
+            if (lane == 0) *C.cnt = 0u;
+            wave_sync();
+            auto col = [&](float y) {
                 const uint32_t key = ykey(y);
-                if (key >= lo && key < hi) L[(nc++) * NT] = __uint_as_float(key);
-            });
-            sort_list(L, nc);
+                if (key >= lo && key < hi) C.list[atomicAdd(C.cnt, 1u)] = __uint_as_float(key);
+            };
+            for (int i = lane; i < w; i += 64) col(rw[aoff + i * astr]);
+            for (int c = lane; c < w; c += 64) col(bv[c]);
+            wave_sync();
+            if (lane < cnt) {  // rank of each value, ties by position
+                const float y = C.list[lane];
+                int r = 0;
+                for (int x = 0; x < cnt; ++x) {
+                    const float yx = C.list[x];
+                    r += (yx < y) || (yx == y && x < lane);
+                }
+                C.sorted[r] = y;
+            }
+            wave_sync();
             *below = base;
-            return nc;
+            return cnt;
         }
         if (stuck) {  // the band spans the whole range: narrow to rank k alone
             r1 = k;
@@ -182,13 +221,14 @@ __device__ int radix_band(const Window &W, int k, int r1, int r2, unsigned *H, f
         shift = max(0, lg - 4);
     }
     *below = base;  // not reached for finite keys
-    L[0] = __uint_as_float(lo);
+    if (lane == 0) C.sorted[0] = __uint_as_float(lo);
+    wave_sync();
     return 1;
 }
 
 // Centred covariance of row r = rb + i and column C0 + u by a direct FP64 dot
 // product (the anchor of a diagonal).
-__device__ __noinline__ float anchor_at(const ProfileJob &J, int64_t rb, int i, int64_t C0, int u) {
+__device__ __forceinline__ float anchor_at(const ProfileJob &J, int64_t rb, int i, int64_t C0, int u) {
     const double *xr = J.row.xc + rb + i;
     const double *xcp = J.col.xc + C0 + u;
     double acc = 0.0;
@@ -237,8 +277,8 @@ __global__ void __launch_bounds__(NT) k_profile(ProfileArgs A) {
         float *c_h = c_dg + CWS;
         float *buf = c_h + CWS;      // V rows x CWS
         float *BM = buf + V * CWS;   // V rows x blocks
-        unsigned *hist = (unsigned *)Ureg;
-        float *lst = (float *)(hist + NB * NT);
+        float *lst = Ureg;                  // selection: CAP x NT per-thread lists
+        float *coop = lst + CAP * NT;       // then per-wave scratch
 
         float *rw = J.rw + (size_t)blockIdx.x * A.B.slot_floats;
         float tmax = 0.0f;
@@ -440,20 +480,22 @@ __global__ void __launch_bounds__(NT) k_profile(ProfileArgs A) {
 
         // 5. selection (eqs. 12-13): k-th smallest y of the w row minima and the
         //    w column minima of each window; thread a takes block a in order.
+        //    Windows whose bracket misses are solved by the whole wave together.
         if (t < nA) {
-            unsigned *H = hist + t;
             float *L = lst + t;
+            const int lane = t & 63;
+            float *cs = coop + (t >> 6) * COOP_FLOATS;
+            const Coop C{(unsigned *)cs, (unsigned *)(cs + NB), cs + NB + 4, cs + NB + 4 + CAP};
             const int r1 = max(1, keff - BAND), r2 = min(2 * w, keff + BAND);
             bool have = false;
-            float blo = 0.0f, bhi = 0.0f;
+            float blo = 0.0f, bhi = 0.0f, ystar = 0.0f;
+            const int astr = G * nA;
             for (int p = 0; p < G; ++p) {
                 const int v = t * G + p;
-                if (v >= JTe) break;
-                Window W{rw, p * nA + t, G * nA, colY + v, w};
-                float ystar = 0.0f;
-                bool done = false;
-                int rlo_below = -1;            // restricted radix: known count below blo
-                for (int attempt = 0; attempt < 2 && have && !done; ++attempt) {
+                const bool valid = v < JTe;
+                bool ok = false;
+                if (valid && have) {
+                    Window W{rw, p * nA + t, astr, colY + v, w};
                     int below = 0, nl = 0;
                     const float lo_ = blo, hi_ = bhi;
                     W.each([&](float y) {
@@ -474,38 +516,31 @@ __global__ void __launch_bounds__(NT) k_profile(ProfileArgs A) {
                         const float sp = (l1 - l0) / (float)max(nl - 1, 1);
                         blo = q1 >= 1 ? L[(q1 - 1) * NT] : l0 - 1.5f * (float)(1 - q1) * sp;
                         bhi = q2 <= nl ? L[(q2 - 1) * NT] : l1 + 1.5f * (float)(q2 - nl) * sp;
-                        done = true;
-                    } else if (nl > CAP && kk >= 1 && kk <= nl) {
-                        rlo_below = below;     // the k-th is inside: search only there
-                        break;
-                    } else {
-                        const float wd = 3.0f * fmaxf(bhi - blo, 1e-6f);
-                        if (kk < 1) {
-                            bhi = blo;
-                            blo = blo - wd;
-                        } else {
-                            blo = bhi;
-                            bhi = bhi + wd;
-                        }
+                        ok = true;
                     }
                 }
-                if (!done) {
-                    int below = 0, nl;
-                    if (rlo_below >= 0 && blo > 0.0f)
-                        nl = radix_band(W, keff, r1, r2, H, L, &below, ykey(blo),
-                                        ykey(bhi) + 1u, rlo_below, 0);
-                    else
-                        nl = radix_band(W, keff, r1, r2, H, L, &below);
-                    const int kk = keff - below;
-                    ystar = L[(min(max(kk, 1), nl) - 1) * NT];
-                    const int q1 = r1 - below, q2 = r2 - below;
-                    blo = L[(min(max(q1, 1), nl) - 1) * NT];
-                    bhi = L[(min(max(q2, 1), nl) - 1) * NT];
-                    have = true;
+                uint64_t need = __ballot(valid && !ok);
+                while (need) {
+                    const int ln = __ffsll((unsigned long long)need) - 1;
+                    need &= need - 1;
+                    const int tf = (t & ~63) + ln;
+                    int below = 0;
+                    const int nc = coop_band(rw, p * nA + tf, astr, colY + tf * G + p, w, keff, r1, r2,
+                                             C, lane, &below);
+                    if (lane == ln) {
+                        const int kk = keff - below;
+                        ystar = C.sorted[min(max(kk, 1), nc) - 1];
+                        blo = C.sorted[min(max(r1 - below, 1), nc) - 1];
+                        bhi = C.sorted[min(max(r2 - below, 1), nc) - 1];
+                        have = true;
+                    }
+                    wave_sync();
                 }
-                const float dist = sqrtf(two_l * fmaxf(ystar, 0.0f));
-                J.D[(int64_t)s * J.ld + J0 + v] = dist;
-                tmax = fmaxf(tmax, dist);
+                if (valid) {
+                    const float dist = sqrtf(two_l * fmaxf(ystar, 0.0f));
+                    J.D[(int64_t)s * J.ld + J0 + v] = dist;
+                    tmax = fmaxf(tmax, dist);
+                }
             }
         }
 
@@ -551,7 +586,7 @@ size_t lds_floats(int w, const Geo &g) {
     const size_t nbl = (cws + G - 1) / G;
     const size_t w4 = ((size_t)w + 3) & ~(size_t)3;
     const size_t dist = 4 * cws + (size_t)g.V * cws + (size_t)g.V * nbl;
-    const size_t sel = (size_t)(NB + CAP) * NT;
+    const size_t sel = (size_t)CAP * NT + (size_t)(NT / 64) * COOP_FLOATS;
     return cwt + 4 * w4 + (dist > sel ? dist : sel);
 }
 
