@@ -307,7 +307,7 @@ int plan_sweep(pst_ctx *c, int64_t n, const int32_t *m_list, int32_t nm, const i
     }
     P->grid = kSweepMaxGrid;
     P->o_rw = o;
-    o = al(o + sizeof(float) * (size_t)kSweepMaxGrid * P->wmax * profile_tile_windows(P->wmax));
+    o = al(o + sizeof(float) * profile_scratch_floats(kSweepMaxGrid, P->wmax));
     P->o_counter = o;
     o = al(o + 256);
     for (int i = 0; i < nm; ++i) {

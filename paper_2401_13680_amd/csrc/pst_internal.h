@@ -12,14 +12,15 @@ constexpr int kProfileThreads = 512;   // threads per profile workgroup (8 wave6
 constexpr int kMaxW = 1025;            // largest supported w = m - l + 1
 constexpr int kScanBlock = 4096;       // elements per block of the prefix-sum scan
 constexpr int kSumBlock = 8192;        // windows per block of the greedy area sums
+constexpr int kStatsPad = 16;          // zeroed elements after each per-window statistic and the series
 
 // Statistics of the length-l subsequences of one series.  The paper evaluates
 // the distance matrix from dot products, means and standard deviations
 // (section 4.1, eq. 9, after its ref. [7]); means here are of the series
 // centred by its global mean.
 struct Stats {
-    const double *xc;  // series minus its global mean, [len]
-    const double *mu;  // centred mean of each window, [Nl]
+    const double *xc;  // series minus its global mean, [len] (+ kStatsPad zeros)
+    const double *mu;  // centred mean of each window, [Nl] (each per-window array + kStatsPad zeros)
     const float *inv;  // 1 / (sigma * sqrt(l)); 0 for a constant window, [Nl]
     const float *h;    // 0.5 for a constant window, else 0, [Nl]
     const float *df;   // (x[j+l] - x[j]) / 2, [Nl]; 0 at the last window

@@ -9,34 +9,36 @@
 //
 // Every later step is an order statistic, monotone in the Pearson correlation
 // rho of the two subsequences, because d = sqrt(2 l (1 - rho)).  The kernel
-// therefore works on y = 1 - rho (d^2 = 2 l y) and forms one distance per
-// window, from the selected y.
+// therefore works on y = (1 - rho) / 2, clamped to [0, 1] (d^2 = 4 l y), and
+// forms one distance per window, from the selected y.  Clamped y values are
+// non-negative floats, ordered like their bit patterns, so minima, comparisons
+// and sorting run on the bits as unsigned integers.
 //
 // Work unit: a tile of (query, JT consecutive windows), JT = 31 * (number of
 // selection threads).  The tile is computed in sub-tiles of SBW windows; a
 // sub-tile needs the w x (SBW + w - 1) block of the matrix:
 //   1. FP64 anchors: the centred covariance at the first cell of each diagonal
 //      of the block, by a direct dot product (register-blocked along the row).
-//   2. Rows in chunks of V: each thread owns V adjacent diagonals and advances
+//   2. Rows in chunks of 8: each thread owns V adjacent diagonals and advances
 //      them one row at a time with the FP32 centred-covariance recurrence
 //          cov(r+1, c+1) = cov(r, c) + df[r]*dg[c] + df[c]*dg[r];
 //      the statistics of its V columns sit in a register window that slides by
 //      one column per row.  The chunk's y values go to LDS.
-//   3. Column minima of y accumulate in LDS for the whole tile (eq. 10).
-//   4. Sliding row minima of width w (eq. 11), per (row, block of 31 windows):
-//      suffix minima of the block and running minima of the window tails in
-//      registers, whole blocks in between from per-block minima in LDS.  They
-//      go to a per-workgroup scratch slot, block-interleaved so that both the
-//      writes here and the reads below are coalesced.
+//   3. Column minima of y (eq. 10) accumulate in LDS for the sub-tile and go
+//      to a per-workgroup copy for the tile.
+//   4. Sliding row minima of width w (eq. 11): wave r takes row r of the chunk,
+//      lane a the 31 windows of block a: suffix minima of the block and running
+//      minima of the window tails in registers, whole blocks in between from
+//      block minima the wave shares in LDS.  They go to a per-workgroup scratch
+//      slot, laid out so that a selection thread reads 4 rows per load.
 //   5. Selection (eqs. 12-13): thread a takes the 31 windows of block a, in
-//      order.  A run starts with an MSD radix select on the bits of y that
-//      brackets the ranks k-8 .. k+8 and sorts the values inside; each next
-//      window makes one pass that counts the values below that bracket and
-//      collects the ones inside it (adjacent windows share all but a few of
-//      their 2w values, so the k-th value rarely leaves the bracket), and
-//      takes the next bracket from the sorted list.  Windows whose bracket
-//      misses (and the first window of each run) are solved by the 64 lanes of
-//      the wave together, one window at a time, with the radix select, so a
+//      order.  A run starts with a per-thread MSD radix select on the bits of y
+//      that brackets the ranks k-8 .. k+8; each window then makes one pass that
+//      counts the values below the bracket and collects the ones inside it
+//      (adjacent windows share all but a few of their 2w values, so the k-th
+//      value rarely leaves the bracket), sorts the few collected values and
+//      takes the next bracket from them.  Windows whose bracket misses are
+//      solved by the 64 lanes of the wave together, one window at a time, so a
 //      rare miss costs the wave a short cooperative step instead of stalling
 //      every lane.  The result is exact either way.
 //
@@ -55,12 +57,16 @@ constexpr int G = 31;      // windows per block (odd: conflict-free LDS strides)
 constexpr int CAP = 28;    // sorted candidate list capacity
 constexpr int NB = 16;     // radix buckets per level
 constexpr int BAND = 8;    // bracket half-width in ranks
+constexpr int BL = 32;     // values per load batch of a window pass
+constexpr int BMW = 128;   // block minima per row (two blocks per lane at most)
+constexpr int RPAD = 32;   // LDS floats after the row buffer (row-minimum reads past a row end)
 
 struct Geo {
     int JT;     // windows per tile
     int nA;     // selection threads = blocks per tile = JT / G
     int SBW;    // windows per sub-tile (multiple of G)
     int V;      // diagonals per thread
+    int RCH;    // rows per chunk (8, or 4 where LDS is short)
 };
 
 struct ProfileArgs {
@@ -68,50 +74,186 @@ struct ProfileArgs {
     Geo g;
 };
 
-__device__ __forceinline__ uint32_t ykey(float y) { return __float_as_uint(fmaxf(y, 0.0f)); }
+__device__ __forceinline__ uint32_t key_of(float y) { return __float_as_uint(y); }
+// Minimum of two non-negative floats (or +inf) through their bit patterns.
+__device__ __forceinline__ float umin(float a, float b) {
+    return __uint_as_float(min(__float_as_uint(a), __float_as_uint(b)));
+}
 
-// In-place insertion sort of the n values L[0], L[NT], ... (per-thread list).
-__device__ __forceinline__ void sort_list(float *L, int n) {
-    for (int x = 1; x < n; ++x) {
-        const float key = L[x * NT];
-        int j = x - 1;
-        while (j >= 0 && L[j * NT] > key) {
-            L[(j + 1) * NT] = L[j * NT];
-            --j;
+// Sorts a[0..N) ascending with Batcher's odd-even merge network (truncated to
+// N inputs: the missing inputs would be the largest keys and never move).
+template <int N>
+__device__ __forceinline__ void sort_net(uint32_t (&a)[N]) {
+#pragma unroll
+    for (int p = 1; p < N; p += p) {
+#pragma unroll
+        for (int k = p; k > 0; k /= 2) {
+#pragma unroll
+            for (int j = k % p; j + k < N; j += 2 * k) {
+#pragma unroll
+                for (int i = 0; i < k; ++i) {
+                    if (i + j + k < N && (i + j) / (2 * p) == (i + j + k) / (2 * p)) {
+                        const uint32_t x = a[i + j], y = a[i + j + k];
+                        a[i + j] = min(x, y);
+                        a[i + j + k] = max(x, y);
+                    }
+                }
+            }
         }
-        L[(j + 1) * NT] = key;
     }
 }
 
-// Values of one window: A(i) for i < w (row minima) and B(c) for c < w
-// (column minima).  each() visits every value exactly once.
-struct Window {
-    const float *rw;   // scratch slot
-    int aoff, astr;    // A(i) = rw[aoff + i * astr]
-    const float *bv;   // B(c) = bv[c]
-    int w;
-    template <typename F>
-    __device__ __forceinline__ void each(F f) const {
-        int i = 0;
-        for (; i + 16 <= w; i += 16) {
-            float y[16];
+// One thread's pass over the 2w values of a window: first A(i), i < w, the
+// row minima in the scratch buffer R, four consecutive rows per 16-byte load
+// (rows 4q .. 4q+3 at byte offset voff + q * gstr); then B(c) = bv[c], c < w,
+// from LDS.  f(key, valid) sees every value once; padding values of the last
+// batch of each half come with valid = false.  Loads run a batch ahead of use.
+template <typename F>
+__device__ __forceinline__ void window_pass(__amdgpu_buffer_rsrc_t R, uint32_t voff, uint32_t gstr, const float *bv,
+                                            int w, F &&f) {
+    constexpr int BG = BL / 4;  // row groups per batch
+    const int gm1 = (w - 1) >> 2;
+    auto load = [&](uint32_t (&y)[BL], int g0) {
 #pragma unroll
-            for (int e = 0; e < 16; ++e) y[e] = rw[aoff + (i + e) * astr];
+        for (int e = 0; e < BG; ++e) {
+            const int q = min(g0 + e, gm1);
+            const auto v = __builtin_amdgcn_raw_buffer_load_b128(R, (int)voff, (int)((uint32_t)q * gstr), 0);
 #pragma unroll
-            for (int e = 0; e < 16; ++e) f(y[e]);
+            for (int r = 0; r < 4; ++r) y[4 * e + r] = v[r];
         }
-        for (; i < w; ++i) f(rw[aoff + i * astr]);
-        int c = 0;
-        for (; c + 16 <= w; c += 16) {
-            float y[16];
+    };
+    auto use = [&](const uint32_t (&y)[BL], int lim) {
 #pragma unroll
-            for (int e = 0; e < 16; ++e) y[e] = bv[c + e];
+        for (int e = 0; e < BL; ++e) f(y[e], e < lim);
+    };
+    const int nfull = w / BL, rem = w - nfull * BL;
+    uint32_t ya[BL], yb[BL];
+    load(ya, 0);
+    int b = 0;
+    for (; b + 2 <= nfull; b += 2) {
+        load(yb, (b + 1) * BG);
+        use(ya, BL);
+        load(ya, (b + 2) * BG);
+        use(yb, BL);
+    }
+    if (b < nfull) {
+        load(yb, (b + 1) * BG);
+        use(ya, BL);
+        if (rem) use(yb, rem);
+    } else if (rem) {
+        use(ya, rem);
+    }
+    const uint32_t *bk = (const uint32_t *)bv;
+    const int wm1 = w - 1;
+    int c = 0;
+    for (; c + BL <= w; c += BL) {
+        uint32_t y[BL];
 #pragma unroll
-            for (int e = 0; e < 16; ++e) f(y[e]);
-        }
-        for (; c < w; ++c) f(bv[c]);
+        for (int e = 0; e < BL; ++e) y[e] = bk[c + e];
+        use(y, BL);
+    }
+    if (c < w) {
+        uint32_t y[BL];
+#pragma unroll
+        for (int e = 0; e < BL; ++e) y[e] = bk[min(c + e, wm1)];
+        use(y, w - c);
+    }
+}
+
+// Per-thread list of bracket keys at L[x * NT], x <= CAP.  Every key is stored
+// at slot min(nl, CAP); nl advances only for keys inside [lo, lo + span], so
+// slots 0 .. nl-1 end up holding exactly those (no branches, no selects).
+struct Bracket {
+    uint32_t lo, span;
+    int below, nl;
+    uint32_t *L;
+    __device__ __forceinline__ void operator()(uint32_t key, bool valid) {
+        below += (valid && key < lo) ? 1 : 0;
+        const bool inb = valid && key - lo <= span;
+        L[min(nl, CAP) * NT] = key;
+        nl += inb ? 1 : 0;
     }
 };
+
+// Per-thread radix select of the key range [lo, hi) holding ranks r1 .. r2
+// (1-based) of one window's 2w values.  Histograms live in the thread's list
+// slots (bucket NB takes the keys outside the range).  Stops when the range
+// holds at most CAP values or one key.
+__device__ __forceinline__ void lane_band(__amdgpu_buffer_rsrc_t R, uint32_t voff, uint32_t gstr, const float *bv,
+                                          int w, int k, int r1, int r2, uint32_t *H, uint32_t &lo_out,
+                                          uint32_t &hi_out) {
+    uint32_t lo = 0u, hi = 0x7F800000u;
+    int base = 0, shift = -1;
+    bool done = false;
+    for (int level = 0; level < 16; ++level) {
+        if (!__any(!done)) break;
+#pragma unroll
+        for (int b = 0; b <= NB; ++b) H[b * NT] = 0u;
+        // level 0 buckets by pairs of binades, 2^-31 .. 2^1 (bucket b holds
+        // exponents 96+2b and 97+2b; the end buckets take the rest); later
+        // levels split [lo, hi) into NB equal key ranges
+        const bool l0 = level == 0;
+        const int sh = l0 ? 24 : max(shift, 0);
+        const uint32_t kb = l0 ? 48u << 24 : lo;
+        const uint32_t span = hi - lo;
+        window_pass(R, voff, gstr, bv, w, [&](uint32_t key, bool valid) {
+            int b = min(max((int)(key - kb) >> sh, 0), NB - 1);
+            b = (valid && key - lo < span) ? b : NB;                    // lo <= key < hi
+            __hip_atomic_fetch_add(H + b * NT, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+        });
+        int acc = base, b1 = -1, b2 = NB - 1, below1 = base;
+        bool fb2 = false;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const int cb = (int)H[b * NT];
+            if (b1 < 0 && acc + cb >= r1) {
+                b1 = b;
+                below1 = acc;
+            }
+            if (!fb2 && acc + cb >= r2) {
+                b2 = b;
+                fb2 = true;
+            }
+            if (!fb2 || b == b2) acc += cb;
+        }
+        if (b1 < 0) b1 = b2;
+        const int cnt = acc - below1;
+        uint32_t nlo, nhi;
+        if (l0) {
+            nlo = b1 == 0 ? 0u : (uint32_t)(2 * b1 + 96) << 23;
+            nhi = b2 == NB - 1 ? 0x7F800000u : (uint32_t)(2 * b2 + 98) << 23;
+        } else {
+            nlo = lo + ((uint32_t)b1 << sh);
+            const uint64_t e = (uint64_t)lo + ((uint64_t)(b2 + 1) << sh);
+            nhi = (uint32_t)(e < (uint64_t)hi ? e : (uint64_t)hi);
+        }
+        if (!done) {
+            const bool stuck = (nlo == lo && nhi == hi);
+            lo = nlo;
+            hi = nhi;
+            base = below1;
+            if (hi - lo == 1u || cnt <= CAP) {
+                done = true;
+            } else {
+                if (stuck) {  // the band spans the whole range: narrow to rank k alone
+                    r1 = k;
+                    r2 = k;
+                }
+                shift = max(0, (32 - __clz((int)(hi - lo - 1u))) - 4);
+            }
+        }
+    }
+    lo_out = lo;
+    hi_out = hi;
+}
+
+// Workgroup barrier that orders LDS accesses only: global stores issued
+// before it may still be in flight (nothing reads them before a full barrier).
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
 
 // Orders LDS accesses of the lanes of one wave (they execute in lockstep).
 __device__ __forceinline__ void wave_sync() {
@@ -123,26 +265,27 @@ __device__ __forceinline__ void wave_sync() {
 struct Coop {
     unsigned *hist;   // NB counters
     unsigned *cnt;    // 1 counter
-    float *list;      // CAP values
-    float *sorted;    // CAP values
+    uint32_t *list;   // CAP keys
+    uint32_t *sorted; // CAP keys
 };
 constexpr int COOP_FLOATS = NB + 4 + 2 * CAP;
 
 // Exact radix select, by the 64 lanes of a wave together, of the key range
 // holding ranks r1 .. r2 (1-based) of one window's 2w values: A(i) =
-// rw[aoff + i*astr] for i < w and B(c) = bv[c] for c < w.  Every lane gets
-// *below (values under the range) and the count of values in it; those values
-// are left sorted in C.sorted.  If the range cannot be narrowed to CAP values
-// the ranks shrink to k .. k.  Must be called by all lanes of the wave.
-__device__ __forceinline__ int coop_band(const float *rw, int aoff, int astr, const float *bv, int w, int k, int r1,
-                         int r2, const Coop &C, int lane, int *below) {
+// ab[(i >> 2) * gs + (i & 3)] for i < w and B(c) = bv[c] for c < w.  Every
+// lane gets *below (values under the range) and the count of values in it;
+// those keys are left sorted in C.sorted.  If the range cannot be narrowed to
+// CAP values the ranks shrink to k .. k.  Must be called by all lanes of the
+// wave.
+__device__ __forceinline__ int coop_band(const float *ab, int gs, const float *bv, int w, int k, int r1,
+                                         int r2, const Coop &C, int lane, int *below) {
     uint32_t lo = 0u, hi = 0x7F800000u;
     int base = 0, shift = -1;
     for (int level = 0; level < 16; ++level) {
         if (lane < NB) C.hist[lane] = 0u;
         wave_sync();
         auto add = [&](float y) {
-            const uint32_t key = ykey(y);
+            const uint32_t key = key_of(y);
             if (key >= lo && key < hi) {
                 int b;
                 if (shift < 0) b = min(max(((int)(key >> 23) - 96) >> 1, 0), NB - 1);
@@ -150,7 +293,7 @@ __device__ __forceinline__ int coop_band(const float *rw, int aoff, int astr, co
                 atomicAdd(&C.hist[b], 1u);
             }
         };
-        for (int i = lane; i < w; i += 64) add(rw[aoff + i * astr]);
+        for (int i = lane; i < w; i += 64) add(ab[(i >> 2) * gs + (i & 3)]);
         for (int c = lane; c < w; c += 64) add(bv[c]);
         wave_sync();
         int acc = base, b1 = -1, b2 = NB - 1, below1 = base;
@@ -184,7 +327,7 @@ __device__ __forceinline__ int coop_band(const float *rw, int aoff, int astr, co
         base = below1;
         wave_sync();  // every lane has read the histogram
         if (hi - lo == 1u) {  // one key value holds ranks r1 .. r2
-            if (lane == 0) C.sorted[0] = __uint_as_float(lo);
+            if (lane == 0) C.sorted[0] = lo;
             wave_sync();
             *below = base;
             return 1;
@@ -193,17 +336,17 @@ __device__ __forceinline__ int coop_band(const float *rw, int aoff, int astr, co
             if (lane == 0) *C.cnt = 0u;
             wave_sync();
             auto col = [&](float y) {
-                const uint32_t key = ykey(y);
-                if (key >= lo && key < hi) C.list[atomicAdd(C.cnt, 1u)] = __uint_as_float(key);
+                const uint32_t key = key_of(y);
+                if (key >= lo && key < hi) C.list[atomicAdd(C.cnt, 1u)] = key;
             };
-            for (int i = lane; i < w; i += 64) col(rw[aoff + i * astr]);
+            for (int i = lane; i < w; i += 64) col(ab[(i >> 2) * gs + (i & 3)]);
             for (int c = lane; c < w; c += 64) col(bv[c]);
             wave_sync();
-            if (lane < cnt) {  // rank of each value, ties by position
-                const float y = C.list[lane];
+            if (lane < cnt) {  // rank of each key, ties by position
+                const uint32_t y = C.list[lane];
                 int r = 0;
                 for (int x = 0; x < cnt; ++x) {
-                    const float yx = C.list[x];
+                    const uint32_t yx = C.list[x];
                     r += (yx < y) || (yx == y && x < lane);
                 }
                 C.sorted[r] = y;
@@ -221,7 +364,7 @@ __device__ __forceinline__ int coop_band(const float *rw, int aoff, int astr, co
         shift = max(0, lg - 4);
     }
     *below = base;  // not reached for finite keys
-    if (lane == 0) C.sorted[0] = __uint_as_float(lo);
+    if (lane == 0) C.sorted[0] = lo;
     wave_sync();
     return 1;
 }
@@ -236,13 +379,42 @@ __device__ __forceinline__ float anchor_at(const ProfileJob &J, int64_t rb, int 
     return (float)(acc - (double)J.l * J.row.mu[rb + i] * J.col.mu[C0 + u]);
 }
 
-template <int V>
+// LDS carve of one tile.  Distance phase: packed row statistics, packed
+// column statistics and column minima of the sub-tile, per-wave block minima,
+// RCH rows of y.  Each row of y has w-1 columns of margin before column 0 and
+// w+V after the sub-tile, where the cells of the partial diagonals that lie
+// outside the sub-tile land.  Selection phase (same memory): column minima of
+// the tile, per-thread lists, per-wave scratch of the cooperative select.
+struct Carve {
+    float4 *rst;   // rows: {inv/2, df, dg, h/2}
+    float4 *cst;   // cst[u + 1] for column u, -1 <= u <= CS+V: {inv, df, dg, (1-h)/2}; zeros outside
+    float *colS, *BMv, *buf;
+    int ldb, lm;   // row stride of buf; margin before column 0
+    float *colY, *lst, *coop;
+    __device__ Carve(float *sm, int w, int V, int RCH, int CWS, int CWT) {
+        const int w4 = (w + 3) & ~3;
+        const int c4 = (CWS + 8 + 3) & ~3;
+        rst = (float4 *)sm;
+        cst = rst + w4;
+        colS = (float *)(cst + c4);
+        BMv = colS + c4;
+        buf = BMv + (NT / 64) * BMW;
+        lm = w - 1;
+        ldb = (lm + CWS + w + V + 3) & ~3;
+        colY = sm;
+        lst = colY + ((CWT + 3) & ~3);
+        coop = lst + (CAP + 1) * NT;
+    }
+};
+
+template <int V, int RCH>
 __global__ void __launch_bounds__(NT) k_profile(ProfileArgs A) {
     extern __shared__ __align__(16) float sm[];
     __shared__ uint32_t next_tile;
     const Geo g = A.g;
     const int JT = g.JT, nA = g.nA, SBW = g.SBW;
     const int t = threadIdx.x;
+    const int wv = t >> 6, lane = t & 63;
     const int64_t total = A.B.tile_end[A.B.njobs - 1];
     int64_t gt = blockIdx.x;
     if (A.B.counter) {  // tiles handed out by a device work counter
@@ -258,70 +430,76 @@ __global__ void __launch_bounds__(NT) k_profile(ProfileArgs A) {
         const int w = J.w, l = J.l;
         const int64_t ntile = (J.Nm + JT - 1) / JT;
         const int keff = min(J.k, 2 * w);
-        const int w4 = (w + 3) & ~3;
-        const int CWT = JT + w - 1;          // columns of a tile
-        const int CWS = SBW + w - 1;         // columns of a sub-tile
-        const float two_l = (float)(2 * l);
+        const int W4 = (w + 3) >> 2;          // groups of 4 rows in the scratch layout
+        const int pstr = W4 * nA * 4;         // scratch floats per window-in-block
+        const int CWT = JT + w - 1;           // columns of a tile
+        const int CWS = SBW + w - 1;          // columns of a sub-tile
+        const float four_l = (float)(4 * l);
+        const Carve M(sm, w, V, RCH, CWS, CWT);
 
-        // LDS: column minima of the tile and row statistics, then a region
-        // shared by the sub-tile distance phase and the selection phase.
-        float *colY = sm;
-        float *r_inv = colY + ((CWT + 3) & ~3);
-        float *r_df = r_inv + w4;
-        float *r_dg = r_df + w4;
-        float *r_h = r_dg + w4;
-        float *Ureg = r_h + w4;
-        float *c_inv = Ureg;
-        float *c_df = c_inv + CWS;
-        float *c_dg = c_df + CWS;
-        float *c_h = c_dg + CWS;
-        float *buf = c_h + CWS;      // V rows x CWS
-        float *BM = buf + V * CWS;   // V rows x blocks
-        float *lst = Ureg;                  // selection: CAP x NT per-thread lists
-        float *coop = lst + CAP * NT;       // then per-wave scratch
-
-        float *rw = J.rw + (size_t)blockIdx.x * A.B.slot_floats;
+        float *rw = J.rw + (size_t)blockIdx.x * A.B.slot_floats;   // row minima of the tile
+        float *colG = rw + (size_t)pstr * G;                      // column minima of the tile
+        const __amdgpu_buffer_rsrc_t R =
+            __builtin_amdgcn_make_buffer_rsrc(rw, (short)0, (int)(A.B.slot_floats * 4), 0x00020000);
         float tmax = 0.0f;
 
         const int s = (int)(tile / ntile);
         const int64_t J0 = (tile % ntile) * JT;
         const int JTe = (int)min<int64_t>(JT, J.Nm - J0);
-        const int CW = JTe + w - 1;
         const int64_t rb = (int64_t)s * J.row_stride;
 
         __syncthreads();  // the previous tile is done with LDS and the scratch slot
-        for (int u = t; u < CW; u += NT) colY[u] = INFINITY;
+        int crow = 0;     // a constant row (h != 0) takes the general path
         for (int i = t; i < w; i += NT) {
+            // y = (0.5 - h_r/2 - h_c/2) - cov * (inv_r/2) * inv_c: constant
+            // windows (h = 0.5, inv = 0) follow the conventions of the stats
             const int64_t r = rb + i;
-            r_inv[i] = J.row.inv[r];
-            r_df[i] = J.row.df[r];
-            r_dg[i] = J.row.dg[r];
-            r_h[i] = J.row.h[r];
+            const float hr = J.row.h[r];
+            M.rst[i] = make_float4(0.5f * J.row.inv[r], J.row.df[r], J.row.dg[r], 0.5f * hr);
+            crow |= hr != 0.0f;
         }
+        const bool any_const = __syncthreads_or(crow) != 0;
+        // re-anchoring at chunk starts keeps the fast path
+        const bool anchor_chunks = J.anchor_every > 0 && J.anchor_every % RCH == 0;
+        const bool fast_tile = !any_const && (J.anchor_every == 0 || anchor_chunks);
 
         for (int Js = 0; Js < JTe; Js += SBW) {
             const int JSe = min(SBW, JTe - Js);   // windows of this sub-tile
             const int CS = JSe + w - 1;           // its columns
-            const int nbl = (CS + G - 1) / G;
+            const int nbl = (CS + G - 1) / G;     // blocks of G columns
             const bool last = Js + SBW >= JTe;
             const int own = last ? CS : SBW;      // columns whose minima it owns
             const int64_t C0 = J0 + Js;           // first column (series index)
-            __syncthreads();  // previous sub-tile done with the shared region
-            for (int u = t; u < CS; u += NT) {
-                const int64_t c = C0 + u;
-                c_inv[u] = J.col.inv[c];
-                c_df[u] = J.col.df[c];
-                c_dg[u] = J.col.dg[c];
-                c_h[u] = J.col.h[c];
+            const int ldb = M.ldb;
+            lds_barrier();  // previous sub-tile done with the shared region
+            for (int u = t; u < CS + V + 2; u += NT) {
+                // entry u holds column u-1; columns -1 and CS+V (and all past
+                // them, by clamping) read as zeros: df = dg = 0 there, so a
+                // partial diagonal's covariance stays at its anchor until the
+                // diagonal enters the sub-tile
+                float4 c = make_float4(0.0f, 0.0f, 0.0f, 0.5f);
+                if (u >= 1 && u <= CS + V) {
+                    const int64_t cc = C0 + u - 1;
+                    c = make_float4(J.col.inv[cc], J.col.df[cc], J.col.dg[cc], 0.5f - 0.5f * J.col.h[cc]);
+                }
+                M.cst[u] = c;
+                if (u < CS) M.colS[u] = INFINITY;
             }
 
-            // 1. FP64 anchors of this thread's V diagonals d0 .. d0+V-1;
-            //    diagonal d holds the cells (i, u = d - (w-1) + i), 0 <= u < CS.
+            // Thread t owns diagonals t*V .. t*V+V-1; diagonal d holds the
+            // cells (i, u = d - (w-1) + i).  Every thread runs every row; the
+            // cells of a partial diagonal outside 0 <= u < CS go to the row
+            // margins and are never read.
+            const int ndg = CS + w - 1;             // diagonals of the sub-tile
+            const int nT = (ndg + V - 1) / V;       // threads with diagonals
+            const bool act = t < nT;
             const int d0 = t * V;
             const int ub0 = d0 - (w - 1);
-            const bool full = (ub0 >= 0) && (d0 + V - 1 <= CS - 1);
+
+            // 1. FP64 anchors: diagonals starting in row 0 (d >= w-1) at
+            //    (0, d - (w-1)); the others at (w-1-d, 0)
             float cov[V];
-            if (full) {
+            if (act && ub0 >= 0) {
                 const double *xr = J.row.xc + rb;
                 const double *xcp = J.col.xc + C0 + ub0;
                 double acc[V], xs[V];
@@ -352,7 +530,7 @@ __global__ void __launch_bounds__(NT) k_profile(ProfileArgs A) {
                 for (int v = 0; v < V; ++v) {
                     const int d = d0 + v;
                     cov[v] = 0.0f;
-                    if (d < CS + w - 1) {
+                    if (act && d < ndg) {
                         const int i0 = max(0, w - 1 - d);
                         const int u0 = d - (w - 1) + i0;
                         const double *xr = J.row.xc + rb + i0;
@@ -363,161 +541,227 @@ __global__ void __launch_bounds__(NT) k_profile(ProfileArgs A) {
                     }
                 }
             }
-            __syncthreads();
+            lds_barrier();
 
             // register window of column statistics: slot (v + k) % V holds the
-            // column of diagonal v at row phase k
-            float wi[V], wf[V], wg[V], wh[V];
+            // column of diagonal v at row k of the current chunk; row k loads
+            // the column of diagonal V-1 into slot (k + V - 1) % V
+            const int cmax = CS + V + 1;
+            float wi[V], wf[V], wg[V], wa[V];
 #pragma unroll
-            for (int v = 0; v < V; ++v) {
-                const int u = min(max(ub0 + v, 0), CS - 1);
-                wi[v] = c_inv[u];
-                wf[v] = c_df[u];
-                wg[v] = c_dg[u];
-                wh[v] = c_h[u];
+            for (int v = 0; v < V - 1; ++v) {
+                const float4 c = M.cst[min(max(ub0 + v + 1, 0), cmax)];
+                wi[v] = c.x;
+                wf[v] = c.y;
+                wg[v] = c.z;
+                wa[v] = c.w;
             }
 
-            for (int R0 = 0; R0 < w; R0 += V) {
-                const int nr = min(V, w - R0);
-                // 2. rows R0 .. R0+nr-1 of y = 1 - rho
+            for (int R0 = 0; R0 < w; R0 += RCH) {
+                const int nr = min(RCH, w - R0);
+                // 2. rows R0 .. R0+nr-1 of y into buf
+                const bool fast = fast_tile && R0 + RCH <= w;
+                if (act) {
+                    if (fast && anchor_chunks && R0 > 0 && R0 % J.anchor_every == 0) {
+                        // FP64 re-anchor at the chunk start: the FP32 recurrence
+                        // never runs more than anchor_every steps
 #pragma unroll
-                for (int k = 0; k < V; ++k) {
-                    const int i = R0 + k;
-                    if (i < w) {
-                        if (i > 0) {
+                        for (int v = 0; v < V; ++v) {
+                            const int u = ub0 + v + R0;
+                            if (u >= 0 && u < CS) cov[v] = anchor_at(J, rb, R0, C0, u);
+                        }
+                    }
+                    if (fast) {
+                        // all rows present, no constant rows: no branches; the
+                        // chunk's statistics are loaded ahead of its LDS stores
+                        float4 cc[RCH], rr4[RCH];
+#pragma unroll
+                        for (int k = 0; k < RCH; ++k) {
+                            cc[k] = M.cst[min(max(ub0 + V + R0 + k, 0), cmax)];
+                            rr4[k] = M.rst[R0 + k];
+                        }
+#pragma unroll
+                        for (int k = 0; k < RCH; ++k) {
+                            const int i = R0 + k;
                             const int sl = (k + V - 1) % V;
-                            const int u = min(max(ub0 + V - 1 + i, 0), CS - 1);
-                            wi[sl] = c_inv[u];
-                            wf[sl] = c_df[u];
-                            wg[sl] = c_dg[u];
-                            wh[sl] = c_h[u];
-                        }
-                        if (J.anchor_every > 0 && i > 0 && i % J.anchor_every == 0) {
-                            // optional FP64 re-anchor: the FP32 recurrence never
-                            // runs more than anchor_every steps
+                            wi[sl] = cc[k].x;
+                            wf[sl] = cc[k].y;
+                            wg[sl] = cc[k].z;
+                            wa[sl] = cc[k].w;
+                            const float4 r = rr4[k];
+                            float *brow = M.buf + k * ldb + M.lm + ub0 + i;
 #pragma unroll
                             for (int v = 0; v < V; ++v) {
-                                const int u = ub0 + v + i;
-                                if (u >= 0 && u < CS) cov[v] = anchor_at(J, rb, i, C0, u);
+                                const int s2 = (v + k) % V;
+                                brow[v] = __builtin_amdgcn_fmed3f(fmaf(-cov[v] * r.x, wi[s2], wa[s2]), 0.0f, 1.0f);
+                                cov[v] = fmaf(r.y, wg[s2], fmaf(wf[s2], r.z, cov[v]));
                             }
                         }
-                        const float ri = r_inv[i], rf = r_df[i], rg = r_dg[i], rh1 = 1.0f - r_h[i];
-                        float *brow = buf + k * CS;
-                        if (full) {
+                    } else {
 #pragma unroll
-                            for (int v = 0; v < V; ++v) {
-                                const int sl = (v + k) % V;
-                                brow[ub0 + v + i] = fmaf(-cov[v] * ri, wi[sl], rh1 - wh[sl]);
-                                cov[v] = fmaf(rf, wg[sl], fmaf(wf[sl], rg, cov[v]));
-                            }
-                        } else {
+                        for (int k = 0; k < RCH; ++k) {
+                            const int i = R0 + k;
+                            if (i < w) {
+                                const int sl = (k + V - 1) % V;
+                                const float4 c = M.cst[min(max(ub0 + V + i, 0), cmax)];
+                                wi[sl] = c.x;
+                                wf[sl] = c.y;
+                                wg[sl] = c.z;
+                                wa[sl] = c.w;
+                                if (J.anchor_every > 0 && i > 0 && i % J.anchor_every == 0) {
 #pragma unroll
-                            for (int v = 0; v < V; ++v) {
-                                const int sl = (v + k) % V;
-                                const int u = ub0 + v + i;
-                                if (u >= 0) {
-                                    if (u < CS) brow[u] = fmaf(-cov[v] * ri, wi[sl], rh1 - wh[sl]);
-                                    cov[v] = fmaf(rf, wg[sl], fmaf(wf[sl], rg, cov[v]));
+                                    for (int v = 0; v < V; ++v) {
+                                        const int u = ub0 + v + i;
+                                        if (u >= 0 && u < CS) cov[v] = anchor_at(J, rb, i, C0, u);
+                                    }
+                                }
+                                const float4 r = M.rst[i];
+                                float *brow = M.buf + k * ldb + M.lm + ub0 + i;
+#pragma unroll
+                                for (int v = 0; v < V; ++v) {
+                                    const int s2 = (v + k) % V;
+                                    brow[v] = __builtin_amdgcn_fmed3f(fmaf(-cov[v] * r.x, wi[s2], wa[s2] - r.w),
+                                                                      0.0f, 1.0f);
+                                    cov[v] = fmaf(r.y, wg[s2], fmaf(wf[s2], r.z, cov[v]));
                                 }
                             }
                         }
                     }
+                    // the next chunk starts at k = 0: slot v must hold what
+                    // slot (v + RCH) % V holds now
+                    float ti[V], tf[V], tg[V], ta[V];
+#pragma unroll
+                    for (int v = 0; v < V; ++v) {
+                        ti[v] = wi[(v + RCH) % V];
+                        tf[v] = wf[(v + RCH) % V];
+                        tg[v] = wg[(v + RCH) % V];
+                        ta[v] = wa[(v + RCH) % V];
+                    }
+#pragma unroll
+                    for (int v = 0; v < V; ++v) {
+                        wi[v] = ti[v];
+                        wf[v] = tf[v];
+                        wg[v] = tg[v];
+                        wa[v] = ta[v];
+                    }
                 }
-                __syncthreads();
+                lds_barrier();
                 // 3. column minima of y (eq. 10) for the columns this sub-tile owns
                 for (int u = t; u < own; u += NT) {
-                    float mn = colY[Js + u];
-                    for (int rr = 0; rr < nr; ++rr) mn = fminf(mn, buf[rr * CS + u]);
-                    colY[Js + u] = mn;
+                    float mn = M.colS[u];
+                    for (int rr = 0; rr < nr; ++rr) mn = umin(mn, M.buf[rr * ldb + M.lm + u]);
+                    M.colS[u] = mn;
                 }
-                // 4. sliding row minima of width w (eq. 11)
-                const int rr = t / nbl;
-                const int al = t - rr * nbl;   // block inside the sub-tile
-                const bool act = rr < nr;
-                float S[G];
-                if (act) {
-                    const float *src = buf + rr * CS + al * G;
-                    const int lim = CS - al * G;
+                // 4. sliding row minima of width w (eq. 11): wave wv takes row
+                //    R0 + wv, lane al the windows of block al of the sub-tile.
+                //    Columns past CS only reach windows past the sub-tile's last.
+                if (wv < nr) {
+                    const float *row = M.buf + wv * ldb + M.lm;
+                    float *BM = M.BMv + wv * BMW;
+                    const int al = lane;
+                    float S[G];
+                    {
+                        // lanes past the last block repeat it (never read back)
+                        const float *src = row + min(al, nbl - 1) * G;
 #pragma unroll
-                    for (int j = 0; j < G; ++j) S[j] = j < lim ? src[j] : INFINITY;
+                        for (int j = 0; j < G; ++j) S[j] = src[j];
 #pragma unroll
-                    for (int j = G - 2; j >= 0; --j) S[j] = fminf(S[j], S[j + 1]);
-                    BM[rr * nbl + al] = S[0];
-                }
-                __syncthreads();
-                if (act && al * G < JSe) {
-                    const float *row = buf + rr * CS;
-                    const int a = Js / G + al;                 // block inside the tile
-                    const int obase = (R0 + rr) * G * nA + a;  // + p * nA
-                    const int vend = min(G, JSe - al * G);
-                    if (w <= G) {
-                        for (int p = 0; p < vend; ++p) {
-                            const int v = al * G + p;
-                            float mn = INFINITY;
-                            for (int c = 0; c < w; ++c) mn = fminf(mn, row[v + c]);
-                            rw[obase + p * nA] = mn;
-                        }
-                    } else {
-                        const int q = (w - 1) / G;
-                        const int rp = (w - 1) - q * G;
-                        float base = INFINITY;
-                        for (int b = al + 1; b < al + q; ++b) base = fminf(base, BM[rr * nbl + b]);
-                        const int pb = (al + q) * G;
-                        for (int x = 0; x <= rp; ++x) base = fminf(base, row[pb + x]);
-                        // tail: columns al*G + w - 1 + p for p = 1 .. G-1
-                        const int tb = al * G + w - 1;
-                        float pr = base;
+                        for (int j = G - 2; j >= 0; --j) S[j] = umin(S[j], S[j + 1]);
+                    }
+                    BM[al] = S[0];
+                    if (al + 64 < nbl) {  // blocks past the 64th: their minima only
+                        const float *src = row + (al + 64) * G;
+                        float mn = src[0];
 #pragma unroll
-                        for (int p = 0; p < G; ++p) {
-                            if (p > 0) pr = fminf(pr, row[min(tb + p, CS - 1)]);
-                            if (p < vend) rw[obase + p * nA] = fminf(S[p], pr);
+                        for (int j = 1; j < G; ++j) mn = umin(mn, src[j]);
+                        BM[al + 64] = mn;
+                    }
+                    wave_sync();
+                    if (al * G < JSe) {
+                        const int a = Js / G + al;   // block inside the tile
+                        // scratch layout: row i of window p of block a at
+                        // ((p * W4 + i / 4) * nA + a) * 4 + i % 4
+                        const int ri = R0 + wv;
+                        const uint32_t vo = (uint32_t)((((ri >> 2) * nA + a) << 2) + (ri & 3)) * 4u;
+                        if (w <= G) {
+                            for (int p = 0; p < G; ++p) {
+                                const int v = al * G + p;
+                                float mn = row[v];
+                                for (int c = 1; c < w; ++c) mn = umin(mn, row[v + c]);
+                                __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(mn), R, (int)vo,
+                                                                      (int)((uint32_t)(p * pstr) * 4u), 0);
+                            }
+                        } else {
+                            // window p: columns al*G + p .. al*G + p + w - 1 =
+                            // suffix of block al, blocks al+1 .. al+q-1, and the
+                            // columns (al+q)*G .. al*G + w - 1 + p
+                            const int q = (w - 1) / G;
+                            const int rp = (w - 1) - q * G;
+                            float base = INFINITY;
+                            for (int b = al + 1; b < al + q; ++b) base = umin(base, BM[b]);
+                            const float *pb = row + (al + q) * G;
+                            for (int x = 0; x <= rp; ++x) base = umin(base, pb[x]);
+                            const float *tl = row + al * G + w - 1;
+                            float pr = base;
+#pragma unroll
+                            for (int p = 0; p < G; ++p) {
+                                if (p > 0) pr = umin(pr, tl[p]);
+                                __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(umin(S[p], pr)), R, (int)vo,
+                                                                      (int)((uint32_t)(p * pstr) * 4u), 0);
+                            }
                         }
                     }
                 }
-                __syncthreads();
+                lds_barrier();
             }
+            // column minima of the owned columns to the tile's copy
+            for (int u = t; u < own; u += NT) colG[Js + u] = M.colS[u];
         }
 
         // 5. selection (eqs. 12-13): k-th smallest y of the w row minima and the
         //    w column minima of each window; thread a takes block a in order.
         //    Windows whose bracket misses are solved by the whole wave together.
-        if (t < nA) {
-            float *L = lst + t;
-            const int lane = t & 63;
-            float *cs = coop + (t >> 6) * COOP_FLOATS;
-            const Coop C{(unsigned *)cs, (unsigned *)(cs + NB), cs + NB + 4, cs + NB + 4 + CAP};
+        __syncthreads();  // the distance phase is done with LDS; colG is written
+        float *colY = M.colY;
+        for (int u = t; u < CWT; u += NT) colY[u] = u < JTe + w - 1 ? colG[u] : INFINITY;
+        lds_barrier();
+        if (t < nA && (t & ~63) * G < JTe) {  // waves with a window in the tile
+            uint32_t *L = (uint32_t *)M.lst + t;
+            float *cs = M.coop + wv * COOP_FLOATS;
+            const Coop C{(unsigned *)cs, (unsigned *)(cs + NB), (uint32_t *)(cs + NB + 4),
+                         (uint32_t *)(cs + NB + 4 + CAP)};
             const int r1 = max(1, keff - BAND), r2 = min(2 * w, keff + BAND);
-            bool have = false;
-            float blo = 0.0f, bhi = 0.0f, ystar = 0.0f;
-            const int astr = G * nA;
+            uint32_t blo = 0u, bhi = 0u, ystar = 0u;
+            const uint32_t gstr = (uint32_t)nA * 16u;  // bytes between row groups
             for (int p = 0; p < G; ++p) {
                 const int v = t * G + p;
                 const bool valid = v < JTe;
-                bool ok = false;
-                if (valid && have) {
-                    Window W{rw, p * nA + t, astr, colY + v, w};
-                    int below = 0, nl = 0;
-                    const float lo_ = blo, hi_ = bhi;
-                    W.each([&](float y) {
-                        below += y < lo_;
-                        if (y >= lo_ && y <= hi_) {
-                            if (nl < CAP) L[nl * NT] = y;
-                            ++nl;
-                        }
-                    });
-                    const int kk = keff - below;
-                    if (kk >= 1 && kk <= nl && nl <= CAP) {
-                        sort_list(L, nl);
-                        ystar = L[(kk - 1) * NT];
-                        // next bracket: ranks k-BAND .. k+BAND of this window, or
-                        // extrapolated from the list's spacing where it ends early
-                        const int q1 = r1 - below, q2 = r2 - below;
-                        const float l0 = L[0], l1 = L[(nl - 1) * NT];
-                        const float sp = (l1 - l0) / (float)max(nl - 1, 1);
-                        blo = q1 >= 1 ? L[(q1 - 1) * NT] : l0 - 1.5f * (float)(1 - q1) * sp;
-                        bhi = q2 <= nl ? L[(q2 - 1) * NT] : l1 + 1.5f * (float)(q2 - nl) * sp;
-                        ok = true;
-                    }
+                const uint32_t voff = (uint32_t)(p * pstr + 4 * t) * 4u;
+                if (p == 0) {  // run start: the bracket from a radix select
+                    uint32_t klo, khi;
+                    lane_band(R, voff, gstr, colY + v, w, keff, r1, r2, L, klo, khi);
+                    blo = klo;
+                    bhi = khi - 1u;
+                }
+                Bracket Bk{blo, bhi - blo, 0, 0, L};
+                window_pass(R, voff, gstr, colY + v, w, Bk);
+                const int kk = keff - Bk.below, nl = Bk.nl;
+                const bool ok = kk >= 1 && kk <= nl && nl <= CAP;
+                uint32_t srt[CAP];
+#pragma unroll
+                for (int x = 0; x < CAP; ++x) srt[x] = x < nl ? L[x * NT] : 0xFFFFFFFFu;
+                sort_net(srt);
+#pragma unroll
+                for (int x = 0; x < CAP; ++x) L[x * NT] = srt[x];
+                if (ok) {
+                    ystar = L[(kk - 1) * NT];
+                    // next bracket: ranks k-BAND .. k+BAND of this window, or
+                    // extrapolated from the list's spacing where it ends early
+                    const int q1 = r1 - Bk.below, q2 = r2 - Bk.below;
+                    const float l0 = __uint_as_float(L[0]), l1 = __uint_as_float(L[(nl - 1) * NT]);
+                    const float sp = (l1 - l0) / (float)max(nl - 1, 1);
+                    blo = q1 >= 1 ? L[(q1 - 1) * NT] : key_of(fmaxf(l0 - 1.5f * (float)(1 - q1) * sp, 0.0f));
+                    bhi = q2 <= nl ? L[(q2 - 1) * NT] : key_of(l1 + 1.5f * (float)(q2 - nl) * sp);
                 }
                 uint64_t need = __ballot(valid && !ok);
                 while (need) {
@@ -525,19 +769,18 @@ __global__ void __launch_bounds__(NT) k_profile(ProfileArgs A) {
                     need &= need - 1;
                     const int tf = (t & ~63) + ln;
                     int below = 0;
-                    const int nc = coop_band(rw, p * nA + tf, astr, colY + tf * G + p, w, keff, r1, r2,
+                    const int nc = coop_band(rw + p * pstr + 4 * tf, 4 * nA, colY + tf * G + p, w, keff, r1, r2,
                                              C, lane, &below);
                     if (lane == ln) {
-                        const int kk = keff - below;
-                        ystar = C.sorted[min(max(kk, 1), nc) - 1];
+                        const int kk2 = keff - below;
+                        ystar = C.sorted[min(max(kk2, 1), nc) - 1];
                         blo = C.sorted[min(max(r1 - below, 1), nc) - 1];
                         bhi = C.sorted[min(max(r2 - below, 1), nc) - 1];
-                        have = true;
                     }
                     wave_sync();
                 }
                 if (valid) {
-                    const float dist = sqrtf(two_l * fmaxf(ystar, 0.0f));
+                    const float dist = sqrtf(four_l * __uint_as_float(ystar));
                     J.D[(int64_t)s * J.ld + J0 + v] = dist;
                     tmax = fmaxf(tmax, dist);
                 }
@@ -549,7 +792,7 @@ __global__ void __launch_bounds__(NT) k_profile(ProfileArgs A) {
             float mx = tmax;
 #pragma unroll
             for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
-            if ((t & 63) == 0) atomicMax(J.dmax_bits, __float_as_uint(mx));
+            if (lane == 0) atomicMax(J.dmax_bits, __float_as_uint(mx));
         }
         if (A.B.counter) {
             __syncthreads();
@@ -575,22 +818,32 @@ Geo geo_for(int w) {
         g.SBW = 32 * G;
     }
     g.JT = g.nA * G;
-    const int ndiag = g.SBW + 2 * w - 2;
-    g.V = ndiag <= 5 * NT ? 5 : 6;
+    // every diagonal of a sub-tile (SBW + 2w - 2 of them) in one thread's block of V
+    g.V = g.SBW + 2 * w - 2 <= 5 * NT ? 5 : 6;
+    g.RCH = 8;
     return g;
 }
 
 size_t lds_floats(int w, const Geo &g) {
-    const size_t cwt = (((size_t)g.JT + w - 1) + 3) & ~(size_t)3;
+    const size_t cwt4 = (((size_t)g.JT + w - 1) + 3) & ~(size_t)3;
     const size_t cws = (size_t)g.SBW + w - 1;
-    const size_t nbl = (cws + G - 1) / G;
+    const size_t c4 = (cws + 8 + 3) & ~(size_t)3;
     const size_t w4 = ((size_t)w + 3) & ~(size_t)3;
-    const size_t dist = 4 * cws + (size_t)g.V * cws + (size_t)g.V * nbl;
-    const size_t sel = (size_t)CAP * NT + (size_t)(NT / 64) * COOP_FLOATS;
-    return cwt + 4 * w4 + (dist > sel ? dist : sel);
+    const size_t ldb = ((size_t)(w - 1) + cws + w + g.V + 3) & ~(size_t)3;
+    const size_t dist = 4 * w4 + 4 * c4 + c4 + (size_t)(NT / 64) * BMW + (size_t)g.RCH * ldb + RPAD;
+    const size_t sel = cwt4 + (size_t)(CAP + 1) * NT + (size_t)(NT / 64) * COOP_FLOATS;
+    return dist > sel ? dist : sel;
 }
 
 }  // namespace
+
+// rows per chunk: 8, or 4 where the row buffer does not fit in LDS or the
+// register blocks are 6 wide
+static Geo geometry(int w) {
+    Geo g = geo_for(w);
+    if (g.V == 6 || 4 * lds_floats(w, g) > 158 * 1024) g.RCH = 4;
+    return g;
+}
 
 int32_t profile_tile_windows(int32_t w) { return geo_for(w).JT; }
 
@@ -599,11 +852,16 @@ int32_t profile_grid(int64_t tiles) {
     return (int32_t)(tiles < slots ? (tiles > 0 ? tiles : 1) : slots);
 }
 
-size_t profile_scratch_floats(int32_t grid, int32_t w) {
-    return (size_t)grid * w * profile_tile_windows(w);
+// scratch floats of one workgroup: the row minima of a tile (rows padded to
+// 4), then the tile's column minima
+static size_t slot_floats_for(int32_t w) {
+    const size_t JT = (size_t)geo_for(w).JT;
+    return (size_t)((w + 3) & ~3) * JT + ((JT + w - 1 + 3) & ~(size_t)3);
 }
 
-size_t profile_lds_bytes(int32_t w) { return 4 * lds_floats(w, geo_for(w)); }
+size_t profile_scratch_floats(int32_t grid, int32_t w) { return (size_t)grid * slot_floats_for(w); }
+
+size_t profile_lds_bytes(int32_t w) { return 4 * lds_floats(w, geometry(w)); }
 
 int64_t profile_tiles(const ProfileJob &j) {
     const int JT = geo_for(j.w).JT;
@@ -612,11 +870,15 @@ int64_t profile_tiles(const ProfileJob &j) {
 
 static_assert(sizeof(ProfileArgs) <= 4000, "kernel arguments must fit the 4 KB limit");
 
+static const void *kernel_for(const Geo &g) {
+    if (g.V == 5) return g.RCH == 8 ? (const void *)k_profile<5, 8> : (const void *)k_profile<5, 4>;
+    return (const void *)k_profile<6, 4>;
+}
+
 hipError_t profile_prepare(int32_t wmax) {
-    const Geo g = geo_for(wmax);
+    const Geo g = geometry(wmax);
     const size_t lds = 4 * lds_floats(wmax, g);
-    const void *fn = g.V == 5 ? (const void *)k_profile<5> : (const void *)k_profile<6>;
-    return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    return hipFuncSetAttribute(kernel_for(g), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
 hipError_t launch_profile_batch(const ProfileJob *jobs, int n, int32_t grid, uint32_t *counter,
@@ -624,11 +886,11 @@ hipError_t launch_profile_batch(const ProfileJob *jobs, int n, int32_t grid, uin
     if (n < 1 || n > kMaxJobs || grid < 1) return hipErrorInvalidValue;
     int wmax = 0;
     for (int i = 0; i < n; ++i) wmax = jobs[i].w > wmax ? jobs[i].w : wmax;
-    const Geo g = geo_for(wmax);
+    const Geo g = geometry(wmax);
     ProfileArgs a;
     a.g = g;
     a.B.njobs = n;
-    a.B.slot_floats = (size_t)wmax * g.JT;
+    a.B.slot_floats = slot_floats_for(wmax);
     a.B.counter = counter;
     int64_t acc = 0;
     for (int i = 0; i < n; ++i) {
@@ -640,13 +902,12 @@ hipError_t launch_profile_batch(const ProfileJob *jobs, int n, int32_t grid, uin
     const size_t lds = 4 * lds_floats(wmax, g);
     const int cws = g.SBW + wmax - 1;
     const int nbl = (cws + G - 1) / G;
-    // every (row, block) item of a row chunk maps to one thread; every
-    // diagonal of a sub-tile to one thread's register block
-    if (wmax > kMaxW || g.V * nbl > NT || g.V * NT < cws + wmax - 1 || lds > 158 * 1024)
+    // every diagonal of a sub-tile maps to one thread's register block; the
+    // blocks of a row to the lanes of one wave (two blocks per lane at most)
+    if (wmax > kMaxW || g.V * NT < cws + wmax - 1 || g.SBW > 64 * G || nbl > BMW || lds > 158 * 1024)
         return hipErrorInvalidValue;
-    if (g.V == 5) hipLaunchKernelGGL(k_profile<5>, dim3(grid), dim3(NT), lds, st, a);
-    else hipLaunchKernelGGL(k_profile<6>, dim3(grid), dim3(NT), lds, st, a);
-    return hipGetLastError();
+    void *args[] = {&a};
+    return hipLaunchKernel(kernel_for(g), dim3(grid), dim3(NT), args, lds, st);
 }
 
 hipError_t launch_profile(const ProfileJob &job, hipStream_t st) {

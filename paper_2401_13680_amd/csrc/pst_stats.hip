@@ -225,13 +225,22 @@ __global__ void __launch_bounds__(kT) k_winstats(const double *__restrict__ xc, 
                                                  const double *__restrict__ misc,
                                                  double *__restrict__ mu, float *__restrict__ inv,
                                                  float *__restrict__ hh, float *__restrict__ df,
-                                                 float *__restrict__ dg) {
+                                                 float *__restrict__ dg, double *__restrict__ xpad) {
     const int64_t Nl = n - l + 1;
     const int64_t N1 = n + 1;
     const double *Ph = pre, *Pl = pre + N1, *Qh = pre + 2 * N1, *Ql = pre + 3 * N1;
     const double thr = misc[3];
     const double dl = (double)l;
-    for (int64_t j = (int64_t)blockIdx.x * kT + threadIdx.x; j < Nl; j += (int64_t)gridDim.x * kT) {
+    for (int64_t j = (int64_t)blockIdx.x * kT + threadIdx.x; j < Nl + kStatsPad; j += (int64_t)gridDim.x * kT) {
+        if (j >= Nl) {  // zeroed padding: readers may run a few windows past the end
+            mu[j] = 0.0;
+            inv[j] = 0.0f;
+            hh[j] = 0.0f;
+            df[j] = 0.0f;
+            dg[j] = 0.0f;
+            xpad[j - Nl] = 0.0;
+            continue;
+        }
         dd S = dd_add(pre_at(Ph, Pl, j + l), dd_neg(pre_at(Ph, Pl, j)));
         dd Q = dd_add(pre_at(Qh, Ql, j + l), dd_neg(pre_at(Qh, Ql, j)));
         // l^2 var = l * Q - S^2, in double-double
@@ -266,12 +275,12 @@ StatsLayout stats_layout(int64_t len, int32_t l) {
     L.Nl = len - l + 1;
     L.nblk = (int32_t)((len + kScanBlock - 1) / kScanBlock);
     size_t o = 0;
-    L.xc = o;   o = al(o + sizeof(double) * len);
-    L.mu = o;   o = al(o + sizeof(double) * L.Nl);
-    L.inv = o;  o = al(o + sizeof(float) * L.Nl);
-    L.h = o;    o = al(o + sizeof(float) * L.Nl);
-    L.df = o;   o = al(o + sizeof(float) * L.Nl);
-    L.dg = o;   o = al(o + sizeof(float) * L.Nl);
+    L.xc = o;   o = al(o + sizeof(double) * (len + kStatsPad));
+    L.mu = o;   o = al(o + sizeof(double) * (L.Nl + kStatsPad));
+    L.inv = o;  o = al(o + sizeof(float) * (L.Nl + kStatsPad));
+    L.h = o;    o = al(o + sizeof(float) * (L.Nl + kStatsPad));
+    L.df = o;   o = al(o + sizeof(float) * (L.Nl + kStatsPad));
+    L.dg = o;   o = al(o + sizeof(float) * (L.Nl + kStatsPad));
     L.pre = o;  o = al(o + sizeof(double) * 4 * (len + 1));
     L.blk = o;  o = al(o + sizeof(double) * 4 * L.nblk);
     L.part = o; o = al(o + sizeof(double) * 3 * 1024);
@@ -305,11 +314,11 @@ hipError_t launch_series_stats(const double *x, char *base, const StatsLayout &L
     hipLaunchKernelGGL(k_center_block, dim3(L.nblk), dim3(kT), 0, st, x, n, misc, xc, blk);
     hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(64), 0, st, blk, L.nblk);
     hipLaunchKernelGGL(k_prefix, dim3(L.nblk), dim3(kT), 0, st, xc, n, blk, pre);
-    int nw = (int)std::min<int64_t>(4096, (L.Nl + kT - 1) / kT);
+    int nw = (int)std::min<int64_t>(4096, (L.Nl + kStatsPad + kT - 1) / kT);
     if (nw < 1) nw = 1;
     hipLaunchKernelGGL(k_winstats, dim3(nw), dim3(kT), 0, st, xc, n, L.l, pre, misc,
                        (double *)(base + L.mu), (float *)(base + L.inv), (float *)(base + L.h),
-                       (float *)(base + L.df), (float *)(base + L.dg));
+                       (float *)(base + L.df), (float *)(base + L.dg), xc + n);
     return hipGetLastError();
 }
 
