@@ -272,29 +272,44 @@ constexpr int COOP_FLOATS = NB + 4 + 2 * CAP;
 
 // Exact radix select, by the 64 lanes of a wave together, of the key range
 // holding ranks r1 .. r2 (1-based) of one window's 2w values: A(i) =
-// ab[(i >> 2) * gs + (i & 3)] for i < w and B(c) = bv[c] for c < w.  Every
-// lane gets *below (values under the range) and the count of values in it;
-// those keys are left sorted in C.sorted.  If the range cannot be narrowed to
-// CAP values the ranks shrink to k .. k.  Must be called by all lanes of the
-// wave.
-__device__ __forceinline__ int coop_band(const float *ab, int gs, const float *bv, int w, int k, int r1,
-                                         int r2, const Coop &C, int lane, int *below) {
-    uint32_t lo = 0u, hi = 0x7F800000u;
-    int base = 0, shift = -1;
+// ab[(i >> 2) * gs + (i & 3)] for i < w and B(c) = bv[c] for c < w.  The
+// search starts from the key range [lo, hi) that holds rank k, with `base`
+// values below it (what the window's failed bracket pass established).  Every
+// lane gets *below (values under the band found) and the count of values in
+// it; those keys are left sorted in C.sorted.  If the band cannot be narrowed
+// to CAP values the ranks shrink to k .. k.  Each lane keeps its share of the
+// row minima (at most CW values) in registers; the column minima are in LDS.
+// Must be called by all lanes of the wave.
+constexpr int CW = (kMaxW + 63) / 64;
+__device__ __forceinline__ int coop_band(const float *ab, int gs, const float *bv, int w, int k, int r1, int r2,
+                                         uint32_t lo, uint32_t hi, int base, const Coop &C, int lane,
+                                         int *below) {
+    uint32_t ka[CW];
+    const uint32_t *bk = (const uint32_t *)bv;
+    const int nj = (w + 63) >> 6;
+#pragma unroll
+    for (int j = 0; j < CW; ++j) {
+        ka[j] = 0xFFFFFFFFu;  // outside every range
+        if (j < nj) {
+            const int i = lane + 64 * j;
+            if (i < w) ka[j] = key_of(ab[(i >> 2) * gs + (i & 3)]);
+        }
+    }
     for (int level = 0; level < 16; ++level) {
+        const uint32_t span = hi - lo;
+        const int shift = max(0, (32 - __clz((int)(span - 1u))) - 4);
         if (lane < NB) C.hist[lane] = 0u;
         wave_sync();
-        auto add = [&](float y) {
-            const uint32_t key = key_of(y);
-            if (key >= lo && key < hi) {
-                int b;
-                if (shift < 0) b = min(max(((int)(key >> 23) - 96) >> 1, 0), NB - 1);
-                else b = (int)((key - lo) >> shift);
-                atomicAdd(&C.hist[b], 1u);
+#pragma unroll
+        for (int j = 0; j < CW; ++j) {
+            if (j < nj) {
+                if (ka[j] - lo < span) atomicAdd(&C.hist[(ka[j] - lo) >> shift], 1u);
             }
-        };
-        for (int i = lane; i < w; i += 64) add(ab[(i >> 2) * gs + (i & 3)]);
-        for (int c = lane; c < w; c += 64) add(bv[c]);
+        }
+        for (int c = lane; c < w; c += 64) {
+            const uint32_t kc = bk[c];
+            if (kc - lo < span) atomicAdd(&C.hist[(kc - lo) >> shift], 1u);
+        }
         wave_sync();
         int acc = base, b1 = -1, b2 = NB - 1, below1 = base;
         for (int b = 0; b < NB; ++b) {
@@ -312,15 +327,9 @@ __device__ __forceinline__ int coop_band(const float *ab, int gs, const float *b
         }
         if (b1 < 0) b1 = b2;
         const int cnt = acc - below1;  // values in buckets b1 .. b2
-        uint32_t nlo, nhi;
-        if (shift < 0) {
-            nlo = b1 == 0 ? 0u : (uint32_t)(2 * b1 + 96) << 23;
-            nhi = b2 == NB - 1 ? 0x7F800000u : (uint32_t)(2 * b2 + 98) << 23;
-        } else {
-            nlo = lo + ((uint32_t)b1 << shift);
-            const uint64_t e = (uint64_t)lo + ((uint64_t)(b2 + 1) << shift);
-            nhi = (uint32_t)(e < (uint64_t)hi ? e : (uint64_t)hi);
-        }
+        const uint32_t nlo = lo + ((uint32_t)b1 << shift);
+        const uint64_t e = (uint64_t)lo + ((uint64_t)(b2 + 1) << shift);
+        const uint32_t nhi = (uint32_t)(e < (uint64_t)hi ? e : (uint64_t)hi);
         const bool stuck = (nlo == lo && nhi == hi);
         lo = nlo;
         hi = nhi;
@@ -335,12 +344,17 @@ __device__ __forceinline__ int coop_band(const float *ab, int gs, const float *b
         if (cnt <= CAP) {
             if (lane == 0) *C.cnt = 0u;
             wave_sync();
-            auto col = [&](float y) {
-                const uint32_t key = key_of(y);
-                if (key >= lo && key < hi) C.list[atomicAdd(C.cnt, 1u)] = key;
-            };
-            for (int i = lane; i < w; i += 64) col(ab[(i >> 2) * gs + (i & 3)]);
-            for (int c = lane; c < w; c += 64) col(bv[c]);
+            const uint32_t sp = hi - lo;
+#pragma unroll
+            for (int j = 0; j < CW; ++j) {
+                if (j < nj) {
+                    if (ka[j] - lo < sp) C.list[atomicAdd(C.cnt, 1u)] = ka[j];
+                }
+            }
+            for (int c = lane; c < w; c += 64) {
+                const uint32_t kc = bk[c];
+                if (kc - lo < sp) C.list[atomicAdd(C.cnt, 1u)] = kc;
+            }
             wave_sync();
             if (lane < cnt) {  // rank of each key, ties by position
                 const uint32_t y = C.list[lane];
@@ -359,9 +373,6 @@ __device__ __forceinline__ int coop_band(const float *ab, int gs, const float *b
             r1 = k;
             r2 = k;
         }
-        const uint32_t span = hi - lo;
-        const int lg = 32 - __clz((int)(span - 1u));
-        shift = max(0, lg - 4);
     }
     *below = base;  // not reached for finite keys
     if (lane == 0) C.sorted[0] = lo;
@@ -763,14 +774,30 @@ __global__ void __launch_bounds__(NT) k_profile(ProfileArgs A) {
                     blo = q1 >= 1 ? L[(q1 - 1) * NT] : key_of(fmaxf(l0 - 1.5f * (float)(1 - q1) * sp, 0.0f));
                     bhi = q2 <= nl ? L[(q2 - 1) * NT] : key_of(l1 + 1.5f * (float)(q2 - nl) * sp);
                 }
+                // where the k-th value lies, from this pass: below the bracket,
+                // above it, or inside an overflowing list
+                uint32_t flo = 0u, fhi = bhi + 1u;
+                int fbase = 0;
+                if (kk > nl) {
+                    flo = bhi + 1u;
+                    fhi = 0x7F800000u;
+                    fbase = Bk.below + nl;
+                } else if (kk >= 1) {
+                    flo = blo;
+                    fbase = Bk.below;
+                } else {
+                    fhi = blo;
+                }
                 uint64_t need = __ballot(valid && !ok);
                 while (need) {
                     const int ln = __ffsll((unsigned long long)need) - 1;
                     need &= need - 1;
                     const int tf = (t & ~63) + ln;
                     int below = 0;
+                    const uint32_t clo = (uint32_t)__shfl((int)flo, ln), chi = (uint32_t)__shfl((int)fhi, ln);
+                    const int cbase = __shfl(fbase, ln);
                     const int nc = coop_band(rw + p * pstr + 4 * tf, 4 * nA, colY + tf * G + p, w, keff, r1, r2,
-                                             C, lane, &below);
+                                             clo, chi, cbase, C, lane, &below);
                     if (lane == ln) {
                         const int kk2 = keff - below;
                         ystar = C.sorted[min(max(kk2, 1), nc) - 1];
