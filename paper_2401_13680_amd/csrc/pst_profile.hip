@@ -30,7 +30,7 @@
 //      lane a the 31 windows of block a: suffix minima of the block and running
 //      minima of the window tails in registers, whole blocks in between from
 //      block minima the wave shares in LDS.  They go to a per-workgroup scratch
-//      slot, laid out so that a selection thread reads 4 rows per load.
+//      slot, laid out so that a wave's stores and loads are contiguous.
 //   5. Selection (eqs. 12-13): thread a takes the 31 windows of block a, in
 //      order.  A run starts with a per-thread MSD radix select on the bits of y
 //      that brackets the ranks k-8 .. k+8; each window then makes one pass that
@@ -104,22 +104,19 @@ __device__ __forceinline__ void sort_net(uint32_t (&a)[N]) {
 }
 
 // One thread's pass over the 2w values of a window: first A(i), i < w, the
-// row minima in the scratch buffer R, four consecutive rows per 16-byte load
-// (rows 4q .. 4q+3 at byte offset voff + q * gstr); then B(c) = bv[c], c < w,
-// from LDS.  f(key, valid) sees every value once; padding values of the last
-// batch of each half come with valid = false.  Loads run a batch ahead of use.
+// row minima in the scratch buffer R (row i at byte offset voff + i * rstr);
+// then B(c) = bv[c], c < w, from LDS.  f(key, valid) sees every value once;
+// padding values of the last batch of each half come with valid = false.
+// Loads run a batch ahead of use.
 template <typename F>
-__device__ __forceinline__ void window_pass(__amdgpu_buffer_rsrc_t R, uint32_t voff, uint32_t gstr, const float *bv,
+__device__ __forceinline__ void window_pass(__amdgpu_buffer_rsrc_t R, uint32_t voff, uint32_t rstr, const float *bv,
                                             int w, F &&f) {
-    constexpr int BG = BL / 4;  // row groups per batch
-    const int gm1 = (w - 1) >> 2;
-    auto load = [&](uint32_t (&y)[BL], int g0) {
+    const int wm1 = w - 1;
+    auto load = [&](uint32_t (&y)[BL], int i0) {
 #pragma unroll
-        for (int e = 0; e < BG; ++e) {
-            const int q = min(g0 + e, gm1);
-            const auto v = __builtin_amdgcn_raw_buffer_load_b128(R, (int)voff, (int)((uint32_t)q * gstr), 0);
-#pragma unroll
-            for (int r = 0; r < 4; ++r) y[4 * e + r] = v[r];
+        for (int e = 0; e < BL; ++e) {
+            const int i = min(i0 + e, wm1);
+            y[e] = __builtin_amdgcn_raw_buffer_load_b32(R, (int)voff, (int)((uint32_t)i * rstr), 0);
         }
     };
     auto use = [&](const uint32_t (&y)[BL], int lim) {
@@ -131,20 +128,19 @@ __device__ __forceinline__ void window_pass(__amdgpu_buffer_rsrc_t R, uint32_t v
     load(ya, 0);
     int b = 0;
     for (; b + 2 <= nfull; b += 2) {
-        load(yb, (b + 1) * BG);
+        load(yb, (b + 1) * BL);
         use(ya, BL);
-        load(ya, (b + 2) * BG);
+        load(ya, (b + 2) * BL);
         use(yb, BL);
     }
     if (b < nfull) {
-        load(yb, (b + 1) * BG);
+        load(yb, (b + 1) * BL);
         use(ya, BL);
         if (rem) use(yb, rem);
     } else if (rem) {
         use(ya, rem);
     }
     const uint32_t *bk = (const uint32_t *)bv;
-    const int wm1 = w - 1;
     int c = 0;
     for (; c + BL <= w; c += BL) {
         uint32_t y[BL];
@@ -179,7 +175,7 @@ struct Bracket {
 // (1-based) of one window's 2w values.  Histograms live in the thread's list
 // slots (bucket NB takes the keys outside the range).  Stops when the range
 // holds at most CAP values or one key.
-__device__ __forceinline__ void lane_band(__amdgpu_buffer_rsrc_t R, uint32_t voff, uint32_t gstr, const float *bv,
+__device__ __forceinline__ void lane_band(__amdgpu_buffer_rsrc_t R, uint32_t voff, uint32_t rstr, const float *bv,
                                           int w, int k, int r1, int r2, uint32_t *H, uint32_t &lo_out,
                                           uint32_t &hi_out) {
     uint32_t lo = 0u, hi = 0x7F800000u;
@@ -196,7 +192,7 @@ __device__ __forceinline__ void lane_band(__amdgpu_buffer_rsrc_t R, uint32_t vof
         const int sh = l0 ? 24 : max(shift, 0);
         const uint32_t kb = l0 ? 48u << 24 : lo;
         const uint32_t span = hi - lo;
-        window_pass(R, voff, gstr, bv, w, [&](uint32_t key, bool valid) {
+        window_pass(R, voff, rstr, bv, w, [&](uint32_t key, bool valid) {
             int b = min(max((int)(key - kb) >> sh, 0), NB - 1);
             b = (valid && key - lo < span) ? b : NB;                    // lo <= key < hi
             __hip_atomic_fetch_add(H + b * NT, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
@@ -272,7 +268,7 @@ constexpr int COOP_FLOATS = NB + 4 + 2 * CAP;
 
 // Exact radix select, by the 64 lanes of a wave together, of the key range
 // holding ranks r1 .. r2 (1-based) of one window's 2w values: A(i) =
-// ab[(i >> 2) * gs + (i & 3)] for i < w and B(c) = bv[c] for c < w.  The
+// ab[i * gs] for i < w and B(c) = bv[c] for c < w.  The
 // search starts from the key range [lo, hi) that holds rank k, with `base`
 // values below it (what the window's failed bracket pass established).  Every
 // lane gets *below (values under the band found) and the count of values in
@@ -292,7 +288,7 @@ __device__ __forceinline__ int coop_band(const float *ab, int gs, const float *b
         ka[j] = 0xFFFFFFFFu;  // outside every range
         if (j < nj) {
             const int i = lane + 64 * j;
-            if (i < w) ka[j] = key_of(ab[(i >> 2) * gs + (i & 3)]);
+            if (i < w) ka[j] = key_of(ab[(size_t)i * gs]);
         }
     }
     for (int level = 0; level < 16; ++level) {
@@ -441,8 +437,7 @@ __global__ void __launch_bounds__(NT) k_profile(ProfileArgs A) {
         const int w = J.w, l = J.l;
         const int64_t ntile = (J.Nm + JT - 1) / JT;
         const int keff = min(J.k, 2 * w);
-        const int W4 = (w + 3) >> 2;          // groups of 4 rows in the scratch layout
-        const int pstr = W4 * nA * 4;         // scratch floats per window-in-block
+        const int pstr = w * nA;              // scratch floats per window-in-block
         const int CWT = JT + w - 1;           // columns of a tile
         const int CWS = SBW + w - 1;          // columns of a sub-tile
         const float four_l = (float)(4 * l);
@@ -658,10 +653,23 @@ __global__ void __launch_bounds__(NT) k_profile(ProfileArgs A) {
                 }
                 lds_barrier();
                 // 3. column minima of y (eq. 10) for the columns this sub-tile owns
-                for (int u = t; u < own; u += NT) {
-                    float mn = M.colS[u];
-                    for (int rr = 0; rr < nr; ++rr) mn = umin(mn, M.buf[rr * ldb + M.lm + u]);
-                    M.colS[u] = mn;
+                if (nr == RCH) {
+                    for (int u = t; u < own; u += NT) {
+                        const float *col = M.buf + M.lm + u;
+                        float m[RCH];
+#pragma unroll
+                        for (int rr = 0; rr < RCH; ++rr) m[rr] = col[rr * ldb];
+                        float mn = M.colS[u];
+#pragma unroll
+                        for (int rr = 0; rr < RCH; ++rr) mn = umin(mn, m[rr]);
+                        M.colS[u] = mn;
+                    }
+                } else {
+                    for (int u = t; u < own; u += NT) {
+                        float mn = M.colS[u];
+                        for (int rr = 0; rr < nr; ++rr) mn = umin(mn, M.buf[rr * ldb + M.lm + u]);
+                        M.colS[u] = mn;
+                    }
                 }
                 // 4. sliding row minima of width w (eq. 11): wave wv takes row
                 //    R0 + wv, lane al the windows of block al of the sub-tile.
@@ -682,18 +690,20 @@ __global__ void __launch_bounds__(NT) k_profile(ProfileArgs A) {
                     BM[al] = S[0];
                     if (al + 64 < nbl) {  // blocks past the 64th: their minima only
                         const float *src = row + (al + 64) * G;
-                        float mn = src[0];
+                        float X[G];
 #pragma unroll
-                        for (int j = 1; j < G; ++j) mn = umin(mn, src[j]);
+                        for (int j = 0; j < G; ++j) X[j] = src[j];
+                        float mn = X[0];
+#pragma unroll
+                        for (int j = 1; j < G; ++j) mn = umin(mn, X[j]);
                         BM[al + 64] = mn;
                     }
                     wave_sync();
                     if (al * G < JSe) {
                         const int a = Js / G + al;   // block inside the tile
                         // scratch layout: row i of window p of block a at
-                        // ((p * W4 + i / 4) * nA + a) * 4 + i % 4
-                        const int ri = R0 + wv;
-                        const uint32_t vo = (uint32_t)((((ri >> 2) * nA + a) << 2) + (ri & 3)) * 4u;
+                        // (p * w + i) * nA + a
+                        const uint32_t vo = (uint32_t)((R0 + wv) * nA + a) * 4u;
                         if (w <= G) {
                             for (int p = 0; p < G; ++p) {
                                 const int v = al * G + p;
@@ -708,15 +718,21 @@ __global__ void __launch_bounds__(NT) k_profile(ProfileArgs A) {
                             // columns (al+q)*G .. al*G + w - 1 + p
                             const int q = (w - 1) / G;
                             const int rp = (w - 1) - q * G;
+                            // the tail columns, loaded ahead of the stores below
+                            const float *tl = row + al * G + w - 1;
+                            float T[G];
+#pragma unroll
+                            for (int p = 1; p < G; ++p) T[p] = tl[p];
                             float base = INFINITY;
+#pragma unroll 4
                             for (int b = al + 1; b < al + q; ++b) base = umin(base, BM[b]);
                             const float *pb = row + (al + q) * G;
+#pragma unroll 4
                             for (int x = 0; x <= rp; ++x) base = umin(base, pb[x]);
-                            const float *tl = row + al * G + w - 1;
                             float pr = base;
 #pragma unroll
                             for (int p = 0; p < G; ++p) {
-                                if (p > 0) pr = umin(pr, tl[p]);
+                                if (p > 0) pr = umin(pr, T[p]);
                                 __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(umin(S[p], pr)), R, (int)vo,
                                                                       (int)((uint32_t)(p * pstr) * 4u), 0);
                             }
@@ -743,19 +759,19 @@ __global__ void __launch_bounds__(NT) k_profile(ProfileArgs A) {
                          (uint32_t *)(cs + NB + 4 + CAP)};
             const int r1 = max(1, keff - BAND), r2 = min(2 * w, keff + BAND);
             uint32_t blo = 0u, bhi = 0u, ystar = 0u;
-            const uint32_t gstr = (uint32_t)nA * 16u;  // bytes between row groups
+            const uint32_t rstr = (uint32_t)nA * 4u;  // bytes between rows
             for (int p = 0; p < G; ++p) {
                 const int v = t * G + p;
                 const bool valid = v < JTe;
-                const uint32_t voff = (uint32_t)(p * pstr + 4 * t) * 4u;
+                const uint32_t voff = (uint32_t)(p * pstr + t) * 4u;
                 if (p == 0) {  // run start: the bracket from a radix select
                     uint32_t klo, khi;
-                    lane_band(R, voff, gstr, colY + v, w, keff, r1, r2, L, klo, khi);
+                    lane_band(R, voff, rstr, colY + v, w, keff, r1, r2, L, klo, khi);
                     blo = klo;
                     bhi = khi - 1u;
                 }
                 Bracket Bk{blo, bhi - blo, 0, 0, L};
-                window_pass(R, voff, gstr, colY + v, w, Bk);
+                window_pass(R, voff, rstr, colY + v, w, Bk);
                 const int kk = keff - Bk.below, nl = Bk.nl;
                 const bool ok = kk >= 1 && kk <= nl && nl <= CAP;
                 uint32_t srt[CAP];
@@ -796,7 +812,7 @@ __global__ void __launch_bounds__(NT) k_profile(ProfileArgs A) {
                     int below = 0;
                     const uint32_t clo = (uint32_t)__shfl((int)flo, ln), chi = (uint32_t)__shfl((int)fhi, ln);
                     const int cbase = __shfl(fbase, ln);
-                    const int nc = coop_band(rw + p * pstr + 4 * tf, 4 * nA, colY + tf * G + p, w, keff, r1, r2,
+                    const int nc = coop_band(rw + p * pstr + tf, nA, colY + tf * G + p, w, keff, r1, r2,
                                              clo, chi, cbase, C, lane, &below);
                     if (lane == ln) {
                         const int kk2 = keff - below;
@@ -879,11 +895,11 @@ int32_t profile_grid(int64_t tiles) {
     return (int32_t)(tiles < slots ? (tiles > 0 ? tiles : 1) : slots);
 }
 
-// scratch floats of one workgroup: the row minima of a tile (rows padded to
-// 4), then the tile's column minima
+// scratch floats of one workgroup: the row minima of a tile, then the tile's
+// column minima
 static size_t slot_floats_for(int32_t w) {
     const size_t JT = (size_t)geo_for(w).JT;
-    return (size_t)((w + 3) & ~3) * JT + ((JT + w - 1 + 3) & ~(size_t)3);
+    return (size_t)w * JT + ((JT + w - 1 + 3) & ~(size_t)3);
 }
 
 size_t profile_scratch_floats(int32_t grid, int32_t w) { return (size_t)grid * slot_floats_for(w); }
