@@ -29,6 +29,29 @@ OPS_PER_CELL = 8
 PEAK_LANE_OPS = 256 * 64 * 2.4e9
 
 
+TRAFFIC_NOTE = os.path.join(ROOT, "profiles", "k_profile_regimes5_n100000_traffic.md")
+KERNEL_SRC = os.path.join(ROOT, "paper_2401_13680_amd", "csrc", "pst_profile.hip")
+
+
+def measured_traffic():
+    """HBM bytes per profile launch from the committed FETCH_SIZE / WRITE_SIZE
+    measurement, or None once the kernel source differs from the one measured."""
+    import hashlib
+    try:
+        note = open(TRAFFIC_NOTE).read()
+    except OSError:
+        return None
+    fields = {}
+    for line in note.splitlines():
+        if ":" in line and line.startswith("- "):
+            key, _, val = line[2:].partition(":")
+            fields[key.strip()] = val.strip().strip("`")
+    sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    if fields.get("kernel source sha256") != sha or "hbm bytes per launch" not in fields:
+        return None
+    return float(fields["hbm bytes per launch"])
+
+
 def cpu_baseline(x, m, l, k, nseg_sample=3):
     """The FP64 oracle on a bounded sample of segments of the same workload."""
     import oracle
@@ -149,6 +172,8 @@ def main():
     ap.add_argument("--workload", default="regimes5_n100000",
                     choices=["regimes5_n100000", "sweep", "serve"])
     ap.add_argument("--requests", type=int, default=40, help="serve: number of requests")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="end with one 1 GiB device copy (reference for FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py drives exactly one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
@@ -206,9 +231,15 @@ def main():
                     step="stats + all segment profiles + greedy + neighbours"),
         latency_ms=dict(p50=float(np.percentile(lat, 50)), p99=float(np.percentile(lat, 99))),
         roofline=dict(bound="alu", achieved=achieved, peak=peak, unit="Tops/s (VALU lane-ops)",
-                      frac=achieved / peak, traffic=None, kernel="k_profile",
+                      frac=achieved / peak, traffic=measured_traffic(), kernel="k_profile",
                       kernel_ms=k_ms, ops_per_cell=OPS_PER_CELL),
     )
+    if args.calibrate_copy:
+        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")  # 1 GiB
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(x, m, l, k)
     print(json.dumps(out), flush=True)
