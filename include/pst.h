@@ -173,7 +173,8 @@ int pst_admission_simulate(size_t budget, int32_t slots, int32_t count, const si
  *                          bucket [0, 1]; the choice is kept per process and,
  *                          if the environment variable PST_AUTOTUNE_CACHE names
  *                          a file, appended there and read back later
- *   PST_OPT_PROFILE_GRID   persistent workgroups of the sweep launch [0 = 256]
+ *   PST_OPT_PROFILE_GRID   persistent workgroups of the sweep launch [0 = all
+ *                          that are resident at once]
  *   PST_OPT_DYNAMIC_TILES  hand tiles out from a device counter [1, 0]
  *   PST_OPT_SWEEP_BATCHED  one launch for all candidates [1]; 0 runs the
  *                          candidates one after another (the plain path)

@@ -96,7 +96,7 @@ int plan(pst_ctx *c, int64_t n, int32_t m, int32_t l, int32_t k, int32_t K, Layo
     L->Nl = n - l + 1;
     L->Nm = n - m + 1;
     L->ntile = (L->Nm + profile_tile_windows(w) - 1) / profile_tile_windows(w);
-    L->grid = profile_grid(L->ntile * nseg);
+    L->grid = profile_grid(L->ntile * nseg, w);
     L->nblk = (int32_t)((L->Nm + kSumBlock - 1) / kSumBlock);
     L->nblk2 = (int32_t)std::min<int64_t>(1024, (L->Nm + 255) / 256);
     L->sT = stats_layout(n, l);
@@ -277,7 +277,6 @@ struct SweepPlan {
     int out_stride = 0;
 };
 
-constexpr int32_t kSweepMaxGrid = 256;
 
 int plan_sweep(pst_ctx *c, int64_t n, const int32_t *m_list, int32_t nm, const int32_t *l_list,
                int32_t K, SweepPlan *P) {
@@ -305,9 +304,9 @@ int plan_sweep(pst_ctx *c, int64_t n, const int32_t *m_list, int32_t nm, const i
         P->o_stats.push_back(o);
         o = al(o + P->SL.back().total);
     }
-    P->grid = kSweepMaxGrid;
+    P->grid = profile_slots(P->wmax);
     P->o_rw = o;
-    o = al(o + sizeof(float) * profile_scratch_floats(kSweepMaxGrid, P->wmax));
+    o = al(o + sizeof(float) * profile_scratch_floats(P->grid, P->wmax));
     P->o_counter = o;
     o = al(o + 256);
     for (int i = 0; i < nm; ++i) {
@@ -467,11 +466,14 @@ int autotune(pst_ctx *c, const SweepPlan &P, const double *T, char *ws, TuneVal 
     // statistics once, then each candidate configuration of the profile launch
     for (size_t j = 0; j < P.ls.size(); ++j)
         HIPCHK(c, launch_series_stats(T, ws + P.o_stats[j], P.SL[j], c->stream));
-    const int cand[][2] = {{256, 1}, {256, 0}, {192, 1}, {128, 1}};
+    // grid: all resident workgroups, three quarters, half; tiles striped or
+    // handed out by the device counter
+    const int S = P.grid;
+    const int cand[][2] = {{S, 1}, {S, 0}, {S * 3 / 4, 1}, {S / 2, 1}};
     hipEvent_t a, b;
     HIPCHK(c, hipEventCreate(&a));
     HIPCHK(c, hipEventCreate(&b));
-    TuneVal best{256, 1, 1e30f};
+    TuneVal best{S, 1, 1e30f};
     for (const auto &cf : cand) {
         ProfileJob jobs[kMaxJobs];
         const int nj = sweep_jobs(P, ws, cf[0], jobs);
@@ -502,7 +504,7 @@ int autotune(pst_ctx *c, const SweepPlan &P, const double *T, char *ws, TuneVal 
 
 int run_sweep(pst_ctx *c, const SweepPlan &P, const double *T, char *ws, size_t ws_bytes,
               const int32_t *m_list, const int32_t *l_list, std::vector<double> *res) {
-    TuneVal cfg{c->opt_grid > 0 ? std::min(c->opt_grid, kSweepMaxGrid) : kSweepMaxGrid, c->opt_dynamic, 0.0f};
+    TuneVal cfg{c->opt_grid > 0 ? std::min(c->opt_grid, P.grid) : P.grid, c->opt_dynamic, 0.0f};
     if (c->opt_autotune) {
         const int rc = autotune(c, P, T, ws, &cfg);
         if (rc) return rc;
@@ -649,7 +651,7 @@ int pst_mpdist_profile(pst_ctx *ctx, const double *T_dev, int64_t n, const doubl
     j.row = stats_view(ws + L.o_Q, L.sQ);
     j.row_stride = 0;
     j.nq = 1;
-    j.grid = profile_grid(L.ntile);
+    j.grid = profile_grid(L.ntile, L.w);
     HIPCHK(ctx, timed_profile(ctx, j));
     return PST_OK;
 }

@@ -7,8 +7,8 @@
 
 namespace pst {
 
-// Profile kernel geometry (the tile width depends on w: see profile_tile_windows).
-constexpr int kProfileThreads = 512;   // threads per profile workgroup (8 wave64)
+// Profile kernel geometry (workgroup size and tile width depend on w: see
+// profile_tile_windows and profile_slots).
 constexpr int kMaxW = 1025;            // largest supported w = m - l + 1
 constexpr int kScanBlock = 4096;       // elements per block of the prefix-sum scan
 constexpr int kSumBlock = 8192;        // windows per block of the greedy area sums
@@ -49,7 +49,7 @@ struct ProfileJob {
     int32_t m, l, w, k, nq;
     float *D;              // out: D[s * ld + j]
     int64_t ld;
-    float *rw;             // scratch: grid * w * profile_tile_windows(w) floats
+    float *rw;             // scratch: profile_scratch_floats(grid, w) floats
     unsigned *dmax_bits;   // optional: atomic max of D's bit patterns
     int32_t grid;          // persistent workgroups
     int32_t anchor_every;  // > 0: also re-anchor every diagonal at rows i % anchor_every == 0
@@ -70,7 +70,8 @@ hipError_t profile_prepare(int32_t wmax);  // kernel attributes; call outside gr
 hipError_t launch_profile_batch(const ProfileJob *jobs, int n, int32_t grid, uint32_t *counter,
                                 hipStream_t st);
 int32_t profile_tile_windows(int32_t w);  // windows per tile
-int32_t profile_grid(int64_t tiles);
+int32_t profile_slots(int32_t w);                 // profile workgroups resident at once
+int32_t profile_grid(int64_t tiles, int32_t w);   // persistent grid for that many tiles
 size_t profile_scratch_floats(int32_t grid, int32_t w);
 hipError_t launch_profile(const ProfileJob &job, hipStream_t st);
 size_t profile_lds_bytes(int32_t w);   // dynamic LDS of one profile workgroup

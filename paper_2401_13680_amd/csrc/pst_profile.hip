@@ -52,7 +52,6 @@
 namespace pst {
 namespace {
 
-constexpr int NT = kProfileThreads;
 constexpr int G = 31;      // windows per block (odd: conflict-free LDS strides)
 constexpr int CAP = 28;    // sorted candidate list capacity
 constexpr int NB = 16;     // radix buckets per level
@@ -62,6 +61,7 @@ constexpr int BMW = 128;   // block minima per row (two blocks per lane at most)
 constexpr int RPAD = 32;   // LDS floats after the row buffer (row-minimum reads past a row end)
 
 struct Geo {
+    int NT;     // threads per workgroup (512, or 256 with two workgroups per CU)
     int JT;     // windows per tile
     int nA;     // selection threads = blocks per tile = JT / G
     int SBW;    // windows per sub-tile (multiple of G)
@@ -156,9 +156,11 @@ __device__ __forceinline__ void window_pass(__amdgpu_buffer_rsrc_t R, uint32_t v
     }
 }
 
-// Per-thread list of bracket keys at L[x * NT], x <= CAP.  Every key is stored
-// at slot min(nl, CAP); nl advances only for keys inside [lo, lo + span], so
-// slots 0 .. nl-1 end up holding exactly those (no branches, no selects).
+// Per-thread list of bracket keys at L[x * NS], x <= CAP (NS: threads of the
+// workgroup).  Every key is stored at slot min(nl, CAP); nl advances only for
+// keys inside [lo, lo + span], so slots 0 .. nl-1 end up holding exactly those
+// (no branches, no selects).
+template <int NS>
 struct Bracket {
     uint32_t lo, span;
     int below, nl;
@@ -166,7 +168,7 @@ struct Bracket {
     __device__ __forceinline__ void operator()(uint32_t key, bool valid) {
         below += (valid && key < lo) ? 1 : 0;
         const bool inb = valid && key - lo <= span;
-        L[min(nl, CAP) * NT] = key;
+        L[min(nl, CAP) * NS] = key;
         nl += inb ? 1 : 0;
     }
 };
@@ -175,6 +177,7 @@ struct Bracket {
 // (1-based) of one window's 2w values.  Histograms live in the thread's list
 // slots (bucket NB takes the keys outside the range).  Stops when the range
 // holds at most CAP values or one key.
+template <int NS>
 __device__ __forceinline__ void lane_band(__amdgpu_buffer_rsrc_t R, uint32_t voff, uint32_t rstr, const float *bv,
                                           int w, int k, int r1, int r2, uint32_t *H, uint32_t &lo_out,
                                           uint32_t &hi_out) {
@@ -184,7 +187,7 @@ __device__ __forceinline__ void lane_band(__amdgpu_buffer_rsrc_t R, uint32_t vof
     for (int level = 0; level < 16; ++level) {
         if (!__any(!done)) break;
 #pragma unroll
-        for (int b = 0; b <= NB; ++b) H[b * NT] = 0u;
+        for (int b = 0; b <= NB; ++b) H[b * NS] = 0u;
         // level 0 buckets by pairs of binades, 2^-31 .. 2^1 (bucket b holds
         // exponents 96+2b and 97+2b; the end buckets take the rest); later
         // levels split [lo, hi) into NB equal key ranges
@@ -195,13 +198,13 @@ __device__ __forceinline__ void lane_band(__amdgpu_buffer_rsrc_t R, uint32_t vof
         window_pass(R, voff, rstr, bv, w, [&](uint32_t key, bool valid) {
             int b = min(max((int)(key - kb) >> sh, 0), NB - 1);
             b = (valid && key - lo < span) ? b : NB;                    // lo <= key < hi
-            __hip_atomic_fetch_add(H + b * NT, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+            __hip_atomic_fetch_add(H + b * NS, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
         });
         int acc = base, b1 = -1, b2 = NB - 1, below1 = base;
         bool fb2 = false;
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
-            const int cb = (int)H[b * NT];
+            const int cb = (int)H[b * NS];
             if (b1 < 0 && acc + cb >= r1) {
                 b1 = b;
                 below1 = acc;
@@ -386,6 +389,58 @@ __device__ __forceinline__ float anchor_at(const ProfileJob &J, int64_t rb, int 
     return (float)(acc - (double)J.l * J.row.mu[rb + i] * J.col.mu[C0 + u]);
 }
 
+// FP64 anchors (centred covariance at the first cell) of a thread's V
+// diagonals d0 .. d0+V-1 of a sub-tile: xr[q] is the centred series at the
+// query's row q, xc[q] at column q of the sub-tile (LDS or global memory).
+// Diagonals starting in row 0 (ub0 = d0-(w-1) >= 0) are register-blocked along
+// row 0; the others start at (w-1-d, 0).
+template <int V>
+__device__ __forceinline__ void diag_anchors(float (&cov)[V], const double *xr, const double *xc, bool act,
+                                             int d0, int w, int l, int ndg, const double *mur, const double *muc) {
+    const int ub0 = d0 - (w - 1);
+    if (act && ub0 >= 0) {
+        const double *xcp = xc + ub0;
+        double acc[V], xs[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) acc[v] = 0.0;
+#pragma unroll
+        for (int v = 0; v < V - 1; ++v) xs[v] = xcp[v];
+        int tt = 0;
+        for (; tt + V <= l; tt += V) {
+#pragma unroll
+            for (int kq = 0; kq < V; ++kq) {
+                xs[(kq + V - 1) % V] = xcp[tt + kq + V - 1];
+                const double a = xr[tt + kq];
+#pragma unroll
+                for (int v = 0; v < V; ++v) acc[v] = fma(a, xs[(kq + v) % V], acc[v]);
+            }
+        }
+        for (; tt < l; ++tt) {
+            const double a = xr[tt];
+#pragma unroll
+            for (int v = 0; v < V; ++v) acc[v] = fma(a, xcp[tt + v], acc[v]);
+        }
+        const double mr = (double)l * mur[0];
+#pragma unroll
+        for (int v = 0; v < V; ++v) cov[v] = (float)(acc[v] - mr * muc[ub0 + v]);
+    } else {
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            const int d = d0 + v;
+            cov[v] = 0.0f;
+            if (act && d < ndg) {
+                const int i0 = max(0, w - 1 - d);
+                const int u0 = d - (w - 1) + i0;
+                const double *xrp = xr + i0;
+                const double *xcp = xc + u0;
+                double acc = 0.0;
+                for (int tt = 0; tt < l; ++tt) acc = fma(xrp[tt], xcp[tt], acc);
+                cov[v] = (float)(acc - (double)l * mur[i0] * muc[u0]);
+            }
+        }
+    }
+}
+
 // LDS carve of one tile.  Distance phase: packed row statistics, packed
 // column statistics and column minima of the sub-tile, per-wave block minima,
 // RCH rows of y.  Each row of y has w-1 columns of margin before column 0 and
@@ -398,14 +453,14 @@ struct Carve {
     float *colS, *BMv, *buf;
     int ldb, lm;   // row stride of buf; margin before column 0
     float *colY, *lst, *coop;
-    __device__ Carve(float *sm, int w, int V, int RCH, int CWS, int CWT) {
+    __device__ Carve(float *sm, int NT, int w, int V, int RCH, int CWS, int CWT) {
         const int w4 = (w + 3) & ~3;
         const int c4 = (CWS + 8 + 3) & ~3;
         rst = (float4 *)sm;
         cst = rst + w4;
         colS = (float *)(cst + c4);
         BMv = colS + c4;
-        buf = BMv + (NT / 64) * BMW;
+        buf = BMv + RCH * BMW;
         lm = w - 1;
         ldb = (lm + CWS + w + V + 3) & ~3;
         colY = sm;
@@ -414,8 +469,11 @@ struct Carve {
     }
 };
 
-template <int V, int RCH>
-__global__ void __launch_bounds__(NT) k_profile(ProfileArgs A) {
+template <int NT, int V, int RCH>
+__global__ void __launch_bounds__(NT, 2) k_profile(ProfileArgs A) {
+    constexpr int NW = NT / 64;                    // waves
+    constexpr int RPW = RCH > NW ? RCH / NW : 1;   // rows per wave in the row-minimum step
+    constexpr int LPR = 64 / RPW;                  // lanes (blocks) per row
     extern __shared__ __align__(16) float sm[];
     __shared__ uint32_t next_tile;
     const Geo g = A.g;
@@ -441,7 +499,7 @@ __global__ void __launch_bounds__(NT) k_profile(ProfileArgs A) {
         const int CWT = JT + w - 1;           // columns of a tile
         const int CWS = SBW + w - 1;          // columns of a sub-tile
         const float four_l = (float)(4 * l);
-        const Carve M(sm, w, V, RCH, CWS, CWT);
+        const Carve M(sm, NT, w, V, RCH, CWS, CWT);
 
         float *rw = J.rw + (size_t)blockIdx.x * A.B.slot_floats;   // row minima of the tile
         float *colG = rw + (size_t)pstr * G;                      // column minima of the tile
@@ -502,50 +560,22 @@ __global__ void __launch_bounds__(NT) k_profile(ProfileArgs A) {
             const int d0 = t * V;
             const int ub0 = d0 - (w - 1);
 
-            // 1. FP64 anchors: diagonals starting in row 0 (d >= w-1) at
-            //    (0, d - (w-1)); the others at (w-1-d, 0)
+            // 1. FP64 anchors.  The sub-tile's slice of the centred series
+            //    (columns 0 .. CS+V+l-2, the query's rows 0 .. w+l-2) is staged
+            //    in the row buffer, free until the first chunk, when it fits.
+            const int ncx = CS + V + l;
+            const int nrx = w + l - 1;
+            const bool staged = 2 * (ncx + nrx) <= RCH * ldb;
             float cov[V];
-            if (act && ub0 >= 0) {
-                const double *xr = J.row.xc + rb;
-                const double *xcp = J.col.xc + C0 + ub0;
-                double acc[V], xs[V];
-#pragma unroll
-                for (int v = 0; v < V; ++v) acc[v] = 0.0;
-#pragma unroll
-                for (int v = 0; v < V - 1; ++v) xs[v] = xcp[v];
-                int tt = 0;
-                for (; tt + V <= l; tt += V) {
-#pragma unroll
-                    for (int kq = 0; kq < V; ++kq) {
-                        xs[(kq + V - 1) % V] = xcp[tt + kq + V - 1];
-                        const double a = xr[tt + kq];
-#pragma unroll
-                        for (int v = 0; v < V; ++v) acc[v] = fma(a, xs[(kq + v) % V], acc[v]);
-                    }
-                }
-                for (; tt < l; ++tt) {
-                    const double a = xr[tt];
-#pragma unroll
-                    for (int v = 0; v < V; ++v) acc[v] = fma(a, xcp[tt + v], acc[v]);
-                }
-                const double mr = (double)l * J.row.mu[rb];
-#pragma unroll
-                for (int v = 0; v < V; ++v) cov[v] = (float)(acc[v] - mr * J.col.mu[C0 + ub0 + v]);
+            if (staged) {
+                double *Xc = (double *)M.buf, *Xr = Xc + ncx;
+                for (int q = t; q < ncx; q += NT) Xc[q] = J.col.xc[C0 + q];
+                for (int q = t; q < nrx; q += NT) Xr[q] = J.row.xc[rb + q];
+                lds_barrier();
+                diag_anchors<V>(cov, Xr, Xc, act, d0, w, l, ndg, J.row.mu + rb, J.col.mu + C0);
             } else {
-#pragma unroll
-                for (int v = 0; v < V; ++v) {
-                    const int d = d0 + v;
-                    cov[v] = 0.0f;
-                    if (act && d < ndg) {
-                        const int i0 = max(0, w - 1 - d);
-                        const int u0 = d - (w - 1) + i0;
-                        const double *xr = J.row.xc + rb + i0;
-                        const double *xcp = J.col.xc + C0 + u0;
-                        double acc = 0.0;
-                        for (int tt = 0; tt < l; ++tt) acc = fma(xr[tt], xcp[tt], acc);
-                        cov[v] = (float)(acc - (double)l * J.row.mu[rb + i0] * J.col.mu[C0 + u0]);
-                    }
-                }
+                diag_anchors<V>(cov, J.row.xc + rb, J.col.xc + C0, act, d0, w, l, ndg, J.row.mu + rb,
+                                J.col.mu + C0);
             }
             lds_barrier();
 
@@ -671,13 +701,15 @@ __global__ void __launch_bounds__(NT) k_profile(ProfileArgs A) {
                         M.colS[u] = mn;
                     }
                 }
-                // 4. sliding row minima of width w (eq. 11): wave wv takes row
-                //    R0 + wv, lane al the windows of block al of the sub-tile.
-                //    Columns past CS only reach windows past the sub-tile's last.
-                if (wv < nr) {
-                    const float *row = M.buf + wv * ldb + M.lm;
-                    float *BM = M.BMv + wv * BMW;
-                    const int al = lane;
+                // 4. sliding row minima of width w (eq. 11): each wave takes
+                //    RPW rows of the chunk, LPR lanes per row; lane al takes
+                //    the windows of block al of the sub-tile.  Columns past CS
+                //    only reach windows past the sub-tile's last.
+                const int rr = wv * RPW + lane / LPR;
+                if (rr < nr) {
+                    const float *row = M.buf + rr * ldb + M.lm;
+                    float *BM = M.BMv + rr * BMW;
+                    const int al = lane % LPR;
                     float S[G];
                     {
                         // lanes past the last block repeat it (never read back)
@@ -688,22 +720,22 @@ __global__ void __launch_bounds__(NT) k_profile(ProfileArgs A) {
                         for (int j = G - 2; j >= 0; --j) S[j] = umin(S[j], S[j + 1]);
                     }
                     BM[al] = S[0];
-                    if (al + 64 < nbl) {  // blocks past the 64th: their minima only
-                        const float *src = row + (al + 64) * G;
+                    if (al + LPR < nbl) {  // blocks past the lanes: their minima only
+                        const float *src = row + (al + LPR) * G;
                         float X[G];
 #pragma unroll
                         for (int j = 0; j < G; ++j) X[j] = src[j];
                         float mn = X[0];
 #pragma unroll
                         for (int j = 1; j < G; ++j) mn = umin(mn, X[j]);
-                        BM[al + 64] = mn;
+                        BM[al + LPR] = mn;
                     }
                     wave_sync();
                     if (al * G < JSe) {
                         const int a = Js / G + al;   // block inside the tile
                         // scratch layout: row i of window p of block a at
                         // (p * w + i) * nA + a
-                        const uint32_t vo = (uint32_t)((R0 + wv) * nA + a) * 4u;
+                        const uint32_t vo = (uint32_t)((R0 + rr) * nA + a) * 4u;
                         if (w <= G) {
                             for (int p = 0; p < G; ++p) {
                                 const int v = al * G + p;
@@ -766,11 +798,11 @@ __global__ void __launch_bounds__(NT) k_profile(ProfileArgs A) {
                 const uint32_t voff = (uint32_t)(p * pstr + t) * 4u;
                 if (p == 0) {  // run start: the bracket from a radix select
                     uint32_t klo, khi;
-                    lane_band(R, voff, rstr, colY + v, w, keff, r1, r2, L, klo, khi);
+                    lane_band<NT>(R, voff, rstr, colY + v, w, keff, r1, r2, L, klo, khi);
                     blo = klo;
                     bhi = khi - 1u;
                 }
-                Bracket Bk{blo, bhi - blo, 0, 0, L};
+                Bracket<NT> Bk{blo, bhi - blo, 0, 0, L};
                 window_pass(R, voff, rstr, colY + v, w, Bk);
                 const int kk = keff - Bk.below, nl = Bk.nl;
                 const bool ok = kk >= 1 && kk <= nl && nl <= CAP;
@@ -848,8 +880,44 @@ __global__ void __launch_bounds__(NT) k_profile(ProfileArgs A) {
     }
 }
 
+constexpr int kCUs = 256;                 // compute units of an MI355X
+constexpr size_t kLdsOne = 158 * 1024;    // LDS budget of one workgroup per CU
+constexpr size_t kLdsTwo = 78 * 1024;     // per workgroup with two per CU
+
+size_t lds_floats(int w, const Geo &g) {
+    const size_t cwt4 = (((size_t)g.JT + w - 1) + 3) & ~(size_t)3;
+    const size_t cws = (size_t)g.SBW + w - 1;
+    const size_t c4 = (cws + 8 + 3) & ~(size_t)3;
+    const size_t w4 = ((size_t)w + 3) & ~(size_t)3;
+    const size_t ldb = ((size_t)(w - 1) + cws + w + g.V + 3) & ~(size_t)3;
+    const size_t dist = 4 * w4 + 4 * c4 + c4 + (size_t)g.RCH * BMW + (size_t)g.RCH * ldb + RPAD;
+    const size_t sel = cwt4 + (size_t)(CAP + 1) * g.NT + (size_t)(g.NT / 64) * COOP_FLOATS;
+    return dist > sel ? dist : sel;
+}
+
+// The sub-tile's diagonals (SBW + 2w - 2) must fit the threads' blocks of V,
+// and a row's blocks the lanes given to it (two blocks per lane at most).
+bool geometry_ok(int w, const Geo &g) {
+    const int cws = g.SBW + w - 1;
+    const int nbl = (cws + G - 1) / G;
+    const int rpw = g.RCH > g.NT / 64 ? g.RCH / (g.NT / 64) : 1;
+    const int lpr = 64 / rpw;
+    return w <= kMaxW && g.V * g.NT >= cws + w - 1 && g.SBW <= lpr * G && nbl <= 2 * lpr && nbl <= BMW &&
+           4 * lds_floats(w, g) <= (g.NT == 256 ? kLdsTwo : kLdsOne);
+}
+
+// Two 256-thread workgroups per CU where their LDS fits (so one can select
+// while the other computes), else one of 512 threads.
 Geo geo_for(int w) {
     Geo g;
+    g.NT = 256;
+    g.nA = 256;
+    g.SBW = 32 * G;
+    g.JT = g.nA * G;
+    g.RCH = 8;
+    g.V = g.SBW + 2 * w - 2 <= 5 * 256 ? 5 : 6;
+    if (geometry_ok(w, g)) return g;
+    g.NT = 512;
     if (w <= 257) {
         g.nA = 512;
         g.SBW = 64 * G;
@@ -861,37 +929,22 @@ Geo geo_for(int w) {
         g.SBW = 32 * G;
     }
     g.JT = g.nA * G;
-    // every diagonal of a sub-tile (SBW + 2w - 2 of them) in one thread's block of V
-    g.V = g.SBW + 2 * w - 2 <= 5 * NT ? 5 : 6;
+    g.V = g.SBW + 2 * w - 2 <= 5 * 512 ? 5 : 6;
+    // rows per chunk: 8, or 4 where the row buffer does not fit or the
+    // register blocks are 6 wide
     g.RCH = 8;
+    if (g.V == 6 || 4 * lds_floats(w, g) > kLdsOne) g.RCH = 4;
     return g;
-}
-
-size_t lds_floats(int w, const Geo &g) {
-    const size_t cwt4 = (((size_t)g.JT + w - 1) + 3) & ~(size_t)3;
-    const size_t cws = (size_t)g.SBW + w - 1;
-    const size_t c4 = (cws + 8 + 3) & ~(size_t)3;
-    const size_t w4 = ((size_t)w + 3) & ~(size_t)3;
-    const size_t ldb = ((size_t)(w - 1) + cws + w + g.V + 3) & ~(size_t)3;
-    const size_t dist = 4 * w4 + 4 * c4 + c4 + (size_t)(NT / 64) * BMW + (size_t)g.RCH * ldb + RPAD;
-    const size_t sel = cwt4 + (size_t)(CAP + 1) * NT + (size_t)(NT / 64) * COOP_FLOATS;
-    return dist > sel ? dist : sel;
 }
 
 }  // namespace
 
-// rows per chunk: 8, or 4 where the row buffer does not fit in LDS or the
-// register blocks are 6 wide
-static Geo geometry(int w) {
-    Geo g = geo_for(w);
-    if (g.V == 6 || 4 * lds_floats(w, g) > 158 * 1024) g.RCH = 4;
-    return g;
-}
-
 int32_t profile_tile_windows(int32_t w) { return geo_for(w).JT; }
 
-int32_t profile_grid(int64_t tiles) {
-    const int64_t slots = 256;  // one workgroup per compute unit
+int32_t profile_slots(int32_t w) { return kCUs * (512 / geo_for(w).NT); }
+
+int32_t profile_grid(int64_t tiles, int32_t w) {
+    const int64_t slots = profile_slots(w);
     return (int32_t)(tiles < slots ? (tiles > 0 ? tiles : 1) : slots);
 }
 
@@ -904,7 +957,7 @@ static size_t slot_floats_for(int32_t w) {
 
 size_t profile_scratch_floats(int32_t grid, int32_t w) { return (size_t)grid * slot_floats_for(w); }
 
-size_t profile_lds_bytes(int32_t w) { return 4 * lds_floats(w, geometry(w)); }
+size_t profile_lds_bytes(int32_t w) { return 4 * lds_floats(w, geo_for(w)); }
 
 int64_t profile_tiles(const ProfileJob &j) {
     const int JT = geo_for(j.w).JT;
@@ -914,12 +967,13 @@ int64_t profile_tiles(const ProfileJob &j) {
 static_assert(sizeof(ProfileArgs) <= 4000, "kernel arguments must fit the 4 KB limit");
 
 static const void *kernel_for(const Geo &g) {
-    if (g.V == 5) return g.RCH == 8 ? (const void *)k_profile<5, 8> : (const void *)k_profile<5, 4>;
-    return (const void *)k_profile<6, 4>;
+    if (g.NT == 256) return g.V == 5 ? (const void *)k_profile<256, 5, 8> : (const void *)k_profile<256, 6, 8>;
+    if (g.V == 5) return g.RCH == 8 ? (const void *)k_profile<512, 5, 8> : (const void *)k_profile<512, 5, 4>;
+    return (const void *)k_profile<512, 6, 4>;
 }
 
 hipError_t profile_prepare(int32_t wmax) {
-    const Geo g = geometry(wmax);
+    const Geo g = geo_for(wmax);
     const size_t lds = 4 * lds_floats(wmax, g);
     return hipFuncSetAttribute(kernel_for(g), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
@@ -929,7 +983,7 @@ hipError_t launch_profile_batch(const ProfileJob *jobs, int n, int32_t grid, uin
     if (n < 1 || n > kMaxJobs || grid < 1) return hipErrorInvalidValue;
     int wmax = 0;
     for (int i = 0; i < n; ++i) wmax = jobs[i].w > wmax ? jobs[i].w : wmax;
-    const Geo g = geometry(wmax);
+    const Geo g = geo_for(wmax);
     ProfileArgs a;
     a.g = g;
     a.B.njobs = n;
@@ -943,14 +997,9 @@ hipError_t launch_profile_batch(const ProfileJob *jobs, int n, int32_t grid, uin
         a.B.tile_end[i] = acc;
     }
     const size_t lds = 4 * lds_floats(wmax, g);
-    const int cws = g.SBW + wmax - 1;
-    const int nbl = (cws + G - 1) / G;
-    // every diagonal of a sub-tile maps to one thread's register block; the
-    // blocks of a row to the lanes of one wave (two blocks per lane at most)
-    if (wmax > kMaxW || g.V * NT < cws + wmax - 1 || g.SBW > 64 * G || nbl > BMW || lds > 158 * 1024)
-        return hipErrorInvalidValue;
+    if (!geometry_ok(wmax, g)) return hipErrorInvalidValue;
     void *args[] = {&a};
-    return hipLaunchKernel(kernel_for(g), dim3(grid), dim3(NT), args, lds, st);
+    return hipLaunchKernel(kernel_for(g), dim3(grid), dim3(g.NT), args, lds, st);
 }
 
 hipError_t launch_profile(const ProfileJob &job, hipStream_t st) {
