@@ -175,8 +175,10 @@ struct Bracket {
 
 // Per-thread radix select of the key range [lo, hi) holding ranks r1 .. r2
 // (1-based) of one window's 2w values.  Histograms live in the thread's list
-// slots (bucket NB takes the keys outside the range).  Stops when the range
-// holds at most CAP values or one key.
+// slots (bucket NB takes the keys outside the range).  A thread stops when its
+// range holds at most CAP values or one key; the wave stops once at most two
+// threads are left (a full pass costs the whole wave; those threads' brackets
+// overflow and the wave's cooperative select finishes them).
 template <int NS>
 __device__ __forceinline__ void lane_band(__amdgpu_buffer_rsrc_t R, uint32_t voff, uint32_t rstr, const float *bv,
                                           int w, int k, int r1, int r2, uint32_t *H, uint32_t &lo_out,
@@ -185,7 +187,7 @@ __device__ __forceinline__ void lane_band(__amdgpu_buffer_rsrc_t R, uint32_t vof
     int base = 0, shift = -1;
     bool done = false;
     for (int level = 0; level < 16; ++level) {
-        if (!__any(!done)) break;
+        if (__popcll(__ballot(!done)) <= (level > 0 ? 2 : 0)) break;
 #pragma unroll
         for (int b = 0; b <= NB; ++b) H[b * NS] = 0u;
         // level 0 buckets by pairs of binades, 2^-31 .. 2^1 (bucket b holds
