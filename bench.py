@@ -97,6 +97,13 @@ def sweep_bench(args):
         torch.cuda.synchronize()
         res[mode] = (time.perf_counter() - t0) / args.steps, r["m_best"]
     dt, mb = res["batched_graph"]
+    # labelling of the series by the snippets of the chosen length, scored by
+    # per-element F1 against the generator's regime labels (section 5.2)
+    S = synth.regime_series(n, 3, synth.SHAPES6)
+    r = api.select_length(T, ms, K, owner=True)
+    truth = torch.from_numpy(S.labels.astype(np.int32)).cuda()
+    C = int(S.labels.max()) + 1
+    lab = api.label_f1(r["owner"], truth, r["m_best"], K, C)
     out = dict(metric="MPdist distance-matrix cells/sec on 1 MI355X; p50/p99 request latency",
                value=cells / dt, unit="cells/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
                ms_per_step=dt * 1e3, higher_is_better=True, scaling="weak", vs_baseline=None,
@@ -105,7 +112,9 @@ def sweep_bench(args):
                            cells_per_step=cells, m_best=mb,
                            step="all 15 lengths: stats + profiles in one launch + greedy + criterion, one HIP graph"),
                plain_one_length_at_a_time=dict(value=cells / res["plain"][0], ms_per_step=res["plain"][0] * 1e3),
-               batched_over_plain=res["plain"][0] / dt)
+               batched_over_plain=res["plain"][0] / dt,
+               labelling=dict(m_best=r["m_best"], classes=C, macro_f1=lab["macro_f1"],
+                              f1=[round(v, 4) for v in lab["f1"]]))
     print(json.dumps(out), flush=True)
 
 

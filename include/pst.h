@@ -166,6 +166,26 @@ int pst_server_stats(pst_server *server, uint64_t *completed, double *cells, int
 int pst_admission_simulate(size_t budget, int32_t slots, int32_t count, const size_t *bytes,
                            const double *arrive_ms, const double *service_ms, double *start_ms);
 
+/* Labelling score (the per-element F1 of section 5.2's accuracy experiment).
+ * owner_dev: int32[n-m+1], the greedy rank (0 .. K-1) of each window's nearest
+ * snippet, as written by pst_snippets / pst_select_length (eq. 6).
+ * truth_dev: int32[n], the true class (0 .. C-1) of each element.
+ * The paper does not spell out how snippets label elements; here element t
+ * takes the snippet owning window min(t, n-m), and snippet p stands for the
+ * true class most of its elements have (ties to the lowest class).
+ * Results (host, each optional except macro_f1_host): map_host int32[K], the
+ * class of each snippet; precision_host, recall_host, f1_host double[C], per
+ * true class, TP/(TP+FP), TP/(TP+FN), 2PR/(P+R), 0 where a denominator is 0;
+ * *macro_f1_host, the mean F1 over the classes present in truth.
+ * ws_dev: device workspace of pst_label_workspace_bytes(K, C) bytes, 256-byte
+ * aligned.  Synchronises the context's stream.  PST_EINVAL for K, C out of
+ * range (K <= 2^20, C <= 4096, K*C <= 2^26), m < 1, n < m, or any owner or
+ * class outside its range.  pst_label_workspace_bytes returns 0 for bad K, C. */
+size_t pst_label_workspace_bytes(int32_t K, int32_t C);
+int pst_label_f1(pst_ctx *ctx, const int32_t *owner_dev, int64_t n, int32_t m, int32_t K,
+                 const int32_t *truth_dev, int32_t C, int32_t *map_host, double *precision_host,
+                 double *recall_host, double *f1_host, double *macro_f1_host, void *ws_dev, size_t ws_bytes);
+
 /* Options of a context (value semantics in brackets, default first):
  *   PST_OPT_SWEEP_GRAPH    capture the length sweep as a HIP graph [1, 0]
  *   PST_OPT_AUTOTUNE       tune the persistent grid and tile scheduling of the

@@ -169,6 +169,31 @@ def select_length(T, m_list, K: int, l_list=None, profiles: bool = False, owner:
     return dict(m_best=mb, scores=list(scores), records=_records(recs, K), profiles=prof, owner=own)
 
 
+def label_f1(owner, truth, m: int, K: int, C: int, ctx: Context | None = None):
+    """Labelling score of K snippets (section 5.2's per-element F1): owner is
+    the int32 owner array of snippets() (n-m+1 windows), truth the int32 true
+    class of each of the n elements."""
+    if not (isinstance(owner, torch.Tensor) and owner.is_cuda and owner.dtype == torch.int32):
+        raise TypeError("owner must be an int32 CUDA tensor")
+    if not (isinstance(truth, torch.Tensor) and truth.is_cuda and truth.dtype == torch.int32):
+        raise TypeError("truth must be an int32 CUDA tensor")
+    owner, truth = owner.contiguous(), truth.contiguous()
+    ctx = ctx or context(truth.device.index)
+    n = truth.numel()
+    if owner.numel() != n - m + 1:
+        raise ValueError(f"owner has {owner.numel()} windows, expected n-m+1 = {n - m + 1}")
+    nb = ctx.L.pst_label_workspace_bytes(K, C)
+    if nb == 0:
+        raise PstError(-1, f"bad K={K} or C={C}")
+    ws = ctx.workspace(nb)
+    mp = (c_int32 * K)()
+    prec, rec, f1 = (c_double * C)(), (c_double * C)(), (c_double * C)()
+    macro = c_double()
+    ctx.check(ctx.L.pst_label_f1(ctx.h, _ptr(owner), n, m, K, _ptr(truth), C, mp, prec, rec, f1,
+                                 byref(macro), _ptr(ws), ws.numel()))
+    return dict(map=list(mp), precision=list(prec), recall=list(rec), f1=list(f1), macro_f1=macro.value)
+
+
 class Server:
     """Request server of the library (pst_server_*): admission by device-memory
     footprint and slots, one stream per running request, results kept until

@@ -616,6 +616,76 @@ size_t pst_select_length_workspace_bytes(int64_t n, const int32_t *m_list, int32
     return mx;
 }
 
+namespace {
+// Workspace of the labelling score: confusion counts, then the results.
+struct LabelLayout {
+    size_t conf, bad, map, prec, rec, f1, macro, total;
+};
+bool label_layout(int32_t K, int32_t C, LabelLayout *L) {
+    if (K < 1 || C < 1 || K > (1 << 20) || C > 4096 || (int64_t)K * C > (1 << 26)) return false;
+    size_t o = 0;
+    L->conf = o;  o = al(o + sizeof(unsigned) * (size_t)K * C);
+    L->bad = o;   o = al(o + sizeof(unsigned));
+    L->map = o;   o = al(o + sizeof(int32_t) * K);
+    L->prec = o;  o = al(o + sizeof(double) * C);
+    L->rec = o;   o = al(o + sizeof(double) * C);
+    L->f1 = o;    o = al(o + sizeof(double) * C);
+    L->macro = o; o = al(o + sizeof(double));
+    L->total = o;
+    return true;
+}
+}  // namespace
+
+size_t pst_label_workspace_bytes(int32_t K, int32_t C) {
+    LabelLayout L;
+    return label_layout(K, C, &L) ? L.total : 0;
+}
+
+int pst_label_f1(pst_ctx *ctx, const int32_t *owner_dev, int64_t n, int32_t m, int32_t K,
+                 const int32_t *truth_dev, int32_t C, int32_t *map_host, double *precision_host,
+                 double *recall_host, double *f1_host, double *macro_f1_host, void *ws_dev, size_t ws_bytes) {
+    int rc = begin(ctx);
+    if (rc) return rc;
+    LabelLayout LL;
+    if (!label_layout(K, C, &LL)) return fail(ctx, PST_EINVAL, "bad K=%d or C=%d", K, C);
+    if (m < 1 || n < m) return fail(ctx, PST_EINVAL, "need 1 <= m <= n (n=%lld m=%d)", (long long)n, m);
+    if (!owner_dev || !truth_dev || !macro_f1_host) return fail(ctx, PST_EINVAL, "null pointer argument");
+    if (!ws_dev) return fail(ctx, PST_EINVAL, "workspace is NULL");
+    if (((uintptr_t)ws_dev & 255) != 0) return fail(ctx, PST_EINVAL, "workspace must be 256-byte aligned");
+    if (ws_bytes < LL.total) return fail(ctx, PST_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, LL.total);
+    char *ws = (char *)ws_dev;
+    LabelJob J;
+    J.owner = owner_dev;
+    J.truth = truth_dev;
+    J.n = n;
+    J.m = m;
+    J.K = K;
+    J.C = C;
+    J.lds = false;
+    J.conf = (unsigned *)(ws + LL.conf);
+    J.bad = (unsigned *)(ws + LL.bad);
+    J.map = (int32_t *)(ws + LL.map);
+    J.prec = (double *)(ws + LL.prec);
+    J.rec = (double *)(ws + LL.rec);
+    J.f1 = (double *)(ws + LL.f1);
+    J.macro = (double *)(ws + LL.macro);
+    HIPCHK(ctx, launch_label_f1(J, ctx->stream));
+    unsigned bad = 0;
+    HIPCHK(ctx, hipMemcpyAsync(&bad, J.bad, sizeof bad, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(macro_f1_host, J.macro, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    if (map_host)
+        HIPCHK(ctx, hipMemcpyAsync(map_host, J.map, sizeof(int32_t) * K, hipMemcpyDeviceToHost, ctx->stream));
+    if (precision_host)
+        HIPCHK(ctx, hipMemcpyAsync(precision_host, J.prec, sizeof(double) * C, hipMemcpyDeviceToHost, ctx->stream));
+    if (recall_host)
+        HIPCHK(ctx, hipMemcpyAsync(recall_host, J.rec, sizeof(double) * C, hipMemcpyDeviceToHost, ctx->stream));
+    if (f1_host)
+        HIPCHK(ctx, hipMemcpyAsync(f1_host, J.f1, sizeof(double) * C, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    if (bad) return fail(ctx, PST_EINVAL, "%u elements have an owner outside [0, K) or a class outside [0, C)", bad);
+    return PST_OK;
+}
+
 int pst_set_option(pst_ctx *ctx, int option, int64_t value) {
     if (!ctx) return PST_EINVAL;
     switch (option) {

@@ -115,4 +115,19 @@ struct SweepGather {
 };
 hipError_t launch_gather(const SweepGather &g, hipStream_t st);
 
+// Labelling score: owner array of K snippets against true classes.
+struct LabelJob {
+    const int32_t *owner;  // [n-m+1] greedy rank of each window's nearest snippet
+    const int32_t *truth;  // [n] true class of each element
+    int64_t n;
+    int32_t m, K, C;
+    bool lds;              // confusion counts through LDS (set by the launcher)
+    unsigned *conf;        // [K*C] out
+    unsigned *bad;         // out: elements with a label outside range
+    int32_t *map;          // [K] out: class of each snippet
+    double *prec, *rec, *f1;  // [C] out
+    double *macro;         // out
+};
+hipError_t launch_label_f1(const LabelJob &job, hipStream_t st);
+
 }  // namespace pst
