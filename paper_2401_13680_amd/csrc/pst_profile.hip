@@ -394,52 +394,48 @@ __device__ __forceinline__ float anchor_at(const ProfileJob &J, int64_t rb, int 
 // FP64 anchors (centred covariance at the first cell) of a thread's V
 // diagonals d0 .. d0+V-1 of a sub-tile: xr[q] is the centred series at the
 // query's row q, xc[q] at column q of the sub-tile (LDS or global memory).
-// Diagonals starting in row 0 (ub0 = d0-(w-1) >= 0) are register-blocked along
-// row 0; the others start at (w-1-d, 0).
+// A thread's diagonals either all start in row 0 (ub0 = d0-(w-1) >= 0, first
+// cell (0, ub0+v)) or all start in column 0 (first cell (w-1-d0-v, 0)); both
+// are the sums acc[j] = sum_t P[t] Q[t+j], j < V, register-blocked along t:
+// P = xr, Q = xc + ub0 for the first kind, P = xc, Q = xr + w-1-d0-(V-1) (and
+// j = V-1-v) for the second.  Diagonals d < 0 or d >= ndg get 0.
 template <int V>
 __device__ __forceinline__ void diag_anchors(float (&cov)[V], const double *xr, const double *xc, bool act,
                                              int d0, int w, int l, int ndg, const double *mur, const double *muc) {
+#pragma unroll
+    for (int v = 0; v < V; ++v) cov[v] = 0.0f;
+    if (!act) return;
     const int ub0 = d0 - (w - 1);
-    if (act && ub0 >= 0) {
-        const double *xcp = xc + ub0;
-        double acc[V], xs[V];
+    const bool top = ub0 >= 0;
+    const int base = -ub0 - (V - 1);
+    const double *P = top ? xr : xc;
+    const double *Q = top ? xc + ub0 : xr + base;
+    double acc[V], xs[V];
 #pragma unroll
-        for (int v = 0; v < V; ++v) acc[v] = 0.0;
+    for (int v = 0; v < V; ++v) acc[v] = 0.0;
 #pragma unroll
-        for (int v = 0; v < V - 1; ++v) xs[v] = xcp[v];
-        int tt = 0;
-        for (; tt + V <= l; tt += V) {
+    for (int v = 0; v < V - 1; ++v) xs[v] = Q[v];
+    int tt = 0;
+    for (; tt + V <= l; tt += V) {
 #pragma unroll
-            for (int kq = 0; kq < V; ++kq) {
-                xs[(kq + V - 1) % V] = xcp[tt + kq + V - 1];
-                const double a = xr[tt + kq];
+        for (int kq = 0; kq < V; ++kq) {
+            xs[(kq + V - 1) % V] = Q[tt + kq + V - 1];
+            const double a = P[tt + kq];
 #pragma unroll
-                for (int v = 0; v < V; ++v) acc[v] = fma(a, xs[(kq + v) % V], acc[v]);
-            }
+            for (int v = 0; v < V; ++v) acc[v] = fma(a, xs[(kq + v) % V], acc[v]);
         }
-        for (; tt < l; ++tt) {
-            const double a = xr[tt];
+    }
+    for (; tt < l; ++tt) {
+        const double a = P[tt];
 #pragma unroll
-            for (int v = 0; v < V; ++v) acc[v] = fma(a, xcp[tt + v], acc[v]);
-        }
-        const double mr = (double)l * mur[0];
+        for (int v = 0; v < V; ++v) acc[v] = fma(a, Q[tt + v], acc[v]);
+    }
 #pragma unroll
-        for (int v = 0; v < V; ++v) cov[v] = (float)(acc[v] - mr * muc[ub0 + v]);
-    } else {
-#pragma unroll
-        for (int v = 0; v < V; ++v) {
-            const int d = d0 + v;
-            cov[v] = 0.0f;
-            if (act && d < ndg) {
-                const int i0 = max(0, w - 1 - d);
-                const int u0 = d - (w - 1) + i0;
-                const double *xrp = xr + i0;
-                const double *xcp = xc + u0;
-                double acc = 0.0;
-                for (int tt = 0; tt < l; ++tt) acc = fma(xrp[tt], xcp[tt], acc);
-                cov[v] = (float)(acc - (double)l * mur[i0] * muc[u0]);
-            }
-        }
+    for (int v = 0; v < V; ++v) {
+        const int d = d0 + v;
+        const double c = top ? acc[v] - (double)l * mur[0] * muc[ub0 + v]
+                             : acc[V - 1 - v] - (double)l * mur[base + V - 1 - v] * muc[0];
+        if (d >= 0 && d < ndg) cov[v] = (float)c;
     }
 }
 
@@ -453,7 +449,8 @@ struct Carve {
     float4 *rst;   // rows: {inv/2, df, dg, h/2}
     float4 *cst;   // cst[u + 1] for column u, -1 <= u <= CS+V: {inv, df, dg, (1-h)/2}; zeros outside
     float *colS, *BMv, *buf;
-    int ldb, lm;   // row stride of buf; margin before column 0
+    int ldb, lm;   // row stride of buf; margin before column 0 (w-1, plus V-1 for
+                   // the diagonals d < 0 of the first thread)
     float *colY, *lst, *coop;
     __device__ Carve(float *sm, int NT, int w, int V, int RCH, int CWS, int CWT) {
         const int w4 = (w + 3) & ~3;
@@ -463,7 +460,7 @@ struct Carve {
         colS = (float *)(cst + c4);
         BMv = colS + c4;
         buf = BMv + RCH * BMW;
-        lm = w - 1;
+        lm = w - 1 + V - 1;
         ldb = (lm + CWS + w + V + 3) & ~3;
         colY = sm;
         lst = colY + ((CWT + 3) & ~3);
@@ -552,21 +549,25 @@ __global__ void __launch_bounds__(NT, 2) k_profile(ProfileArgs A) {
                 if (u < CS) M.colS[u] = INFINITY;
             }
 
-            // Thread t owns diagonals t*V .. t*V+V-1; diagonal d holds the
-            // cells (i, u = d - (w-1) + i).  Every thread runs every row; the
-            // cells of a partial diagonal outside 0 <= u < CS go to the row
-            // margins and are never read.
+            // Thread t owns diagonals t*V-off .. t*V-off+V-1, diagonal d the
+            // cells (i, u = d - (w-1) + i); off makes w-1 a multiple of V, so
+            // that no thread holds diagonals of both the lower triangle
+            // (d < w-1) and the rest.  Every thread runs every row; the cells
+            // of a partial diagonal outside 0 <= u < CS, and all cells of the
+            // diagonals d < 0, go to the row margins and are never read.
             const int ndg = CS + w - 1;             // diagonals of the sub-tile
-            const int nT = (ndg + V - 1) / V;       // threads with diagonals
+            const int off = (V - (w - 1) % V) % V;
+            const int nT = (ndg + off + V - 1) / V; // threads with diagonals
             const bool act = t < nT;
-            const int d0 = t * V;
+            const int d0 = t * V - off;
             const int ub0 = d0 - (w - 1);
 
             // 1. FP64 anchors.  The sub-tile's slice of the centred series
-            //    (columns 0 .. CS+V+l-2, the query's rows 0 .. w+l-2) is staged
-            //    in the row buffer, free until the first chunk, when it fits.
+            //    (columns 0 .. CS+V+l-1, the query's rows 0 .. w+l+V-3) is
+            //    staged in the row buffer, free until the first chunk, when it
+            //    fits.
             const int ncx = CS + V + l;
-            const int nrx = w + l - 1;
+            const int nrx = w + l + V - 2;
             const bool staged = 2 * (ncx + nrx) <= RCH * ldb;
             float cov[V];
             if (staged) {
@@ -891,20 +892,21 @@ size_t lds_floats(int w, const Geo &g) {
     const size_t cws = (size_t)g.SBW + w - 1;
     const size_t c4 = (cws + 8 + 3) & ~(size_t)3;
     const size_t w4 = ((size_t)w + 3) & ~(size_t)3;
-    const size_t ldb = ((size_t)(w - 1) + cws + w + g.V + 3) & ~(size_t)3;
+    const size_t ldb = ((size_t)(w - 1 + g.V - 1) + cws + w + g.V + 3) & ~(size_t)3;
     const size_t dist = 4 * w4 + 4 * c4 + c4 + (size_t)g.RCH * BMW + (size_t)g.RCH * ldb + RPAD;
     const size_t sel = cwt4 + (size_t)(CAP + 1) * g.NT + (size_t)(g.NT / 64) * COOP_FLOATS;
     return dist > sel ? dist : sel;
 }
 
-// The sub-tile's diagonals (SBW + 2w - 2) must fit the threads' blocks of V,
+// The sub-tile's diagonals (SBW + 2w - 2, plus up to V-1 below diagonal 0
+// that align the lower triangle to the blocks) must fit the threads' blocks of V,
 // and a row's blocks the lanes given to it (two blocks per lane at most).
 bool geometry_ok(int w, const Geo &g) {
     const int cws = g.SBW + w - 1;
     const int nbl = (cws + G - 1) / G;
     const int rpw = g.RCH > g.NT / 64 ? g.RCH / (g.NT / 64) : 1;
     const int lpr = 64 / rpw;
-    return w <= kMaxW && g.V * g.NT >= cws + w - 1 && g.SBW <= lpr * G && nbl <= 2 * lpr && nbl <= BMW &&
+    return w <= kMaxW && g.V * g.NT >= cws + w - 1 + g.V - 1 && g.SBW <= lpr * G && nbl <= 2 * lpr && nbl <= BMW &&
            4 * lds_floats(w, g) <= (g.NT == 256 ? kLdsTwo : kLdsOne);
 }
 
@@ -917,7 +919,7 @@ Geo geo_for(int w) {
     g.SBW = 32 * G;
     g.JT = g.nA * G;
     g.RCH = 8;
-    g.V = g.SBW + 2 * w - 2 <= 5 * 256 ? 5 : 6;
+    g.V = g.SBW + 2 * w - 2 + 4 <= 5 * 256 ? 5 : 6;
     if (geometry_ok(w, g)) return g;
     g.NT = 512;
     if (w <= 257) {
@@ -931,7 +933,7 @@ Geo geo_for(int w) {
         g.SBW = 32 * G;
     }
     g.JT = g.nA * G;
-    g.V = g.SBW + 2 * w - 2 <= 5 * 512 ? 5 : 6;
+    g.V = g.SBW + 2 * w - 2 + 4 <= 5 * 512 ? 5 : 6;
     // rows per chunk: 8, or 4 where the row buffer does not fit or the
     // register blocks are 6 wide
     g.RCH = 8;
