@@ -165,11 +165,23 @@ struct Bracket {
     uint32_t lo, span;
     int below, nl;
     uint32_t *L;
+    // An invalid key becomes 0xFFFFFFFF, which is neither below lo nor inside
+    // (span < 2^31).  Four VALU operations count it: the borrow of key - lo
+    // is carried into below, the range test into nl.
     __device__ __forceinline__ void operator()(uint32_t key, bool valid) {
-        below += (valid && key < lo) ? 1 : 0;
-        const bool inb = valid && key - lo <= span;
+        key = valid ? key : 0xFFFFFFFFu;
         L[min(nl, CAP) * NS] = key;
-        nl += inb ? 1 : 0;
+        uint32_t d;
+        asm("v_sub_co_u32_e32 %0, vcc, %2, %3\n\t"
+            "v_addc_co_u32_e32 %1, vcc, 0, %1, vcc"
+            : "=v"(d), "+v"(below)
+            : "v"(key), "v"(lo)
+            : "vcc");
+        asm("v_cmp_le_u32_e32 vcc, %1, %2\n\t"
+            "v_addc_co_u32_e32 %0, vcc, 0, %0, vcc"
+            : "+v"(nl)
+            : "v"(d), "v"(span)
+            : "vcc");
     }
 };
 
