@@ -118,6 +118,51 @@ def sweep_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def multi_bench(args):
+    """Multivariate: 4 coordinates of 100 000 points switching regime together,
+    m=256, l=128, K=4 per coordinate; every coordinate's profiles in one
+    launch against one coordinate after another."""
+    import numpy as np
+    import torch
+
+    from paper_2401_13680_amd import api, synth
+
+    wl = synth.WORKLOADS["multi4_n100000"]
+    n, d, m, l, K = wl["n"], wl["d"], wl["m"], wl["l"], wl["K"]
+    S = synth.multivariate_series(n, d, 6)
+    X = torch.from_numpy(S.x).cuda()
+    cells = d * (n // m) * (m - l + 1) * (n - l + 1)
+    res = {}
+    for mode in ("batched", "plain"):
+        def step():
+            if mode == "batched":
+                return api.snippets_multi(X, m, l, K, owner=True)
+            return [api.snippets(X[j], m, l, K, owner=True) for j in range(d)]
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            r = step()
+        torch.cuda.synchronize()
+        res[mode] = ((time.perf_counter() - t0) / args.steps, r)
+    dt, r = res["batched"]
+    same = all(r[j]["records"] == res["plain"][1][j]["records"] for j in range(d))
+    truth = torch.from_numpy(S.labels.astype(np.int32)).cuda()
+    C = int(S.labels.max()) + 1
+    f1 = [api.label_f1(r[j]["owner"], truth, m, K, C)["macro_f1"] for j in range(d)]
+    out = dict(metric="MPdist distance-matrix cells/sec on 1 MI355X; p50/p99 request latency",
+               value=cells / dt, unit="cells/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
+               ms_per_step=dt * 1e3, higher_is_better=True, scaling="weak", vs_baseline=None,
+               dtype="f32", data="synthetic",
+               config=dict(workload="multi4_n100000", n=n, d=d, m=m, l=l, K=K, cells_per_step=cells,
+                           step="stats of every coordinate + all profiles in one launch + greedy + neighbours"),
+               plain_one_coordinate_at_a_time=dict(value=cells / res["plain"][0], ms_per_step=res["plain"][0] * 1e3),
+               batched_over_plain=res["plain"][0] / dt, batched_equals_plain=same,
+               labelling=dict(classes=C, macro_f1_per_coordinate=[round(v, 4) for v in f1]))
+    print(json.dumps(out), flush=True)
+
+
 def serve_bench(args):
     """Serving: Poisson arrivals (20 / s) of regime-switching series with n
     log-uniform in [1e4, 5e5], m in {64, .., 1024}, l = m/2, K in 3..5."""
@@ -179,7 +224,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="regimes5_n100000",
-                    choices=["regimes5_n100000", "sweep", "serve"])
+                    choices=["regimes5_n100000", "sweep", "serve", "multi"])
     ap.add_argument("--requests", type=int, default=40, help="serve: number of requests")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="end with one 1 GiB device copy (reference for FETCH_SIZE / WRITE_SIZE counters)")
@@ -191,6 +236,8 @@ def main():
         return sweep_bench(args)
     if args.workload == "serve":
         return serve_bench(args)
+    if args.workload == "multi":
+        return multi_bench(args)
 
     import numpy as np
     import torch

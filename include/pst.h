@@ -113,6 +113,24 @@ int pst_snippets(pst_ctx *ctx, const double *T_dev, int64_t n, int32_t m, int32_
                  int32_t k, int32_t K, pst_snippet *out_host, float *profiles_dev,
                  int32_t *owner_dev, float *dmax_host, void *ws_dev, size_t ws_bytes);
 
+/* Multivariate series (eqs. 1-2): d coordinates of length n, coordinate j
+ * at T_dev + j*ld (float64, ld >= n).  Section 3.2 runs the snippet search on
+ * each coordinate independently; here every coordinate's profile set runs in
+ * one persistent launch (one job per coordinate), then each coordinate's
+ * greedy search and neighbours.  Results equal d calls of pst_snippets.
+ *   out_host   pst_snippet[d][K], row j for coordinate j, ordered as in
+ *              pst_snippets
+ *   owner_dev  int32[d][n-m+1] (may be NULL), row j as pst_snippets' owner_dev
+ *   dmax_host  float32[d] (may be NULL), max of each coordinate's D
+ * The workspace must hold pst_snippets_multi_workspace_bytes(d, n, m, l, K)
+ * bytes (256-byte aligned; 0 is returned for invalid sizes).  Errors as
+ * pst_snippets, plus PST_EINVAL if d < 1 or d > 16 or ld < n, naming the first
+ * coordinate that holds a non-finite value. */
+size_t pst_snippets_multi_workspace_bytes(int32_t d, int64_t n, int32_t m, int32_t l, int32_t K);
+int pst_snippets_multi(pst_ctx *ctx, const double *T_dev, int32_t d, int64_t ld, int64_t n,
+                       int32_t m, int32_t l, int32_t k, int32_t K, pst_snippet *out_host,
+                       int32_t *owner_dev, float *dmax_host, void *ws_dev, size_t ws_bytes);
+
 /* eq. 18 over num_m (1..16) candidate lengths m_list (l_list NULL: l = m/2; k
  * is the default of each m).  scores_host: float64[num_m] (may be NULL).
  * m_best receives the argmax (ties to the smallest m); out_host /

@@ -19,6 +19,9 @@ numpy float64 (0-based indices; the paper is 1-based):
   eq. 16-17  representativeness curve M and ProfileArea
   eq. 6-8    neighbours, frac and the ordering of snippets
   eq. 18     the snippet-length criterion
+  eq. 1-2    a multivariate series: section 3.2 searches each coordinate on
+             its own, so the multivariate result is the list of the
+             coordinates' results
 
 Readings taken where the text is garbled or silent (each is also listed in the
 design notes): sliding window width w = m-l+1 in eq. 11; element min(k, 2w) in
@@ -236,3 +239,11 @@ def select_length(x: np.ndarray, m_list, K: int, l_list=None, k_list=None):
         results.append(r)
     best = max(range(len(m_list)), key=lambda i: (scores[i], -m_list[i]))
     return dict(m_best=int(m_list[best]), scores=scores, results=results)
+
+
+def snippets_multi(X: np.ndarray, m: int, l: int, K: int, k: int | None = None):
+    """Snippets of a d-coordinate series X (d x n, eqs. 1-2): section 3.2 runs
+    the search on every coordinate independently."""
+    X = np.asarray(X, dtype=np.float64)
+    assert X.ndim == 2
+    return [snippets(X[j], m, l, K, k) for j in range(X.shape[0])]

@@ -67,6 +67,9 @@ def load():
         "pst_select_length": (c_int, [P, P, c_int64, POINTER(c_int32), c_int32, POINTER(c_int32),
                                       c_int32, POINTER(c_int32), POINTER(c_double),
                                       POINTER(Snippet), P, P, P, c_size_t]),
+        "pst_snippets_multi_workspace_bytes": (c_size_t, [c_int32, c_int64, c_int32, c_int32, c_int32]),
+        "pst_snippets_multi": (c_int, [P, P, c_int32, c_int64, c_int64, c_int32, c_int32, c_int32, c_int32,
+                                       POINTER(Snippet), P, POINTER(c_float), P, c_size_t]),
         "pst_set_timing": (c_int, [P, c_int]),
         "pst_set_option": (c_int, [P, c_int, c_int64]),
         "pst_server_create": (c_int, [POINTER(P), c_int, c_size_t, c_int32]),

@@ -131,6 +131,31 @@ def snippets(T, m: int, l: int, K: int, k: int = 0, profiles: bool = False, owne
     return dict(records=_records(recs, K), profiles=prof, owner=own, dmax=float(dmax.value))
 
 
+def snippets_multi(X, m: int, l: int, K: int, k: int = 0, owner: bool = False, ctx: Context | None = None):
+    """Snippets of every coordinate of a multivariate series X (d x n, float64,
+    on the GPU), the coordinates searched independently (section 3.2) in one
+    batched profile launch.  Returns one pst_snippets-style result per
+    coordinate."""
+    if not (isinstance(X, torch.Tensor) and X.is_cuda and X.dtype == torch.float64 and X.dim() == 2):
+        raise TypeError("X must be a 2-D float64 CUDA tensor (d x n)")
+    if X.stride(1) != 1:
+        raise ValueError("X must have unit stride along the series")
+    ctx = ctx or context(X.device.index)
+    d, n = X.shape
+    nb = ctx.L.pst_snippets_multi_workspace_bytes(d, n, m, l, K)
+    if nb == 0:
+        raise PstError(-1, f"invalid sizes d={d} n={n} m={m} l={l} K={K}")
+    Nm = n - m + 1
+    own = torch.empty((d, Nm), dtype=torch.int32, device=X.device) if owner else None
+    recs = (Snippet * (d * K))()
+    dmax = (c_float * d)()
+    ws = ctx.workspace(nb)
+    ctx.check(ctx.L.pst_snippets_multi(ctx.h, _ptr(X), d, X.stride(0), n, m, l, k, K, recs, _ptr(own), dmax,
+                                        _ptr(ws), ws.numel()))
+    return [dict(records=_records(recs[j * K:(j + 1) * K], K), owner=None if own is None else own[j],
+                 dmax=float(dmax[j])) for j in range(d)]
+
+
 def select_length(T, m_list, K: int, l_list=None, profiles: bool = False, owner: bool = False,
                   batched: bool = True, graph: bool = True, autotune: bool = False,
                   ctx: Context | None = None):

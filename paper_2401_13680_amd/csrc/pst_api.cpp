@@ -78,7 +78,9 @@ struct Layout {
 int32_t eff_k(int32_t k, int32_t m) { return k > 0 ? k : (m + 9) / 10; }
 
 // Validate sizes; on success fill the layout.  K == 0 means "no snippets".
-int plan(pst_ctx *c, int64_t n, int32_t m, int32_t l, int32_t k, int32_t K, Layout *L) {
+// Without with_rw the profile kernel's scratch is left out (a batch that
+// shares one scratch region supplies it).
+int plan(pst_ctx *c, int64_t n, int32_t m, int32_t l, int32_t k, int32_t K, Layout *L, bool with_rw = true) {
     if (m < 2 || n < m) return fail(c, PST_EINVAL, "need 2 <= m <= n (m=%d, n=%lld)", m, (long long)n);
     if (l < 2 || l > m) return fail(c, PST_EINVAL, "need 2 <= l <= m (l=%d, m=%d)", l, m);
     const int32_t w = m - l + 1;
@@ -104,7 +106,7 @@ int plan(pst_ctx *c, int64_t n, int32_t m, int32_t l, int32_t k, int32_t K, Layo
     size_t o = 0;
     L->o_T = o;      o = al(o + L->sT.total);
     L->o_Q = o;      o = al(o + L->sQ.total);
-    L->o_rw = o;     o = al(o + sizeof(float) * profile_scratch_floats(L->grid, w));
+    L->o_rw = o;     o = al(o + (with_rw ? sizeof(float) * profile_scratch_floats(L->grid, w) : 0));
     L->o_D = o;      o = al(o + sizeof(float) * (size_t)nseg * L->Nm);
     L->o_M = o;      o = al(o + sizeof(float) * L->Nm);
     L->o_part = o;   o = al(o + sizeof(double) * (size_t)nseg * L->nblk);
@@ -255,6 +257,78 @@ int collect_records(pst_ctx *c, const Layout &L, char *ws, pst_snippet *out, flo
     return PST_OK;
 }
 
+
+// ---------------------------------------------------------------- multivariate
+// The snippet search runs on each coordinate of a d-dimensional series on its
+// own (section 3.2, over the coordinates of eqs. 1-2): one profile job per
+// coordinate, all of them in one persistent launch over a shared scratch
+// region, then each coordinate's greedy search and neighbours.
+struct MultiPlan {
+    Layout L;          // one coordinate's region (without profile scratch)
+    int32_t d = 0, grid = 0;
+    size_t o_rw = 0, o_counter = 0, total = 0;
+};
+
+int plan_multi(pst_ctx *c, int32_t d, int64_t n, int32_t m, int32_t l, int32_t k, int32_t K, MultiPlan *P) {
+    if (d < 1 || d > kMaxJobs) return fail(c, PST_EINVAL, "need 1 <= d <= %d coordinates (d=%d)", kMaxJobs, d);
+    if (K < 1) return fail(c, PST_EINVAL, "need K >= 1 (K=%d)", K);
+    const int rc = plan(c, n, m, l, k, K, &P->L, false);
+    if (rc) return rc;
+    P->d = d;
+    P->grid = profile_grid(P->L.ntile * P->L.nseg * d, P->L.w);
+    size_t o = (size_t)d * P->L.total;
+    P->o_rw = o;       o = al(o + sizeof(float) * profile_scratch_floats(P->grid, P->L.w));
+    P->o_counter = o;  o = al(o + 256);
+    P->total = o;
+    return PST_OK;
+}
+
+int run_multi(pst_ctx *c, const MultiPlan &P, const double *T, int64_t ldT, char *ws, pst_snippet *out,
+              int32_t *owner, float *dmax_host) {
+    const Layout &L = P.L;
+    auto region = [&](int j) { return ws + (size_t)j * L.total; };
+    // statistics of every coordinate; one sync for the finiteness checks
+    std::vector<double> misc((size_t)P.d * 4);
+    for (int j = 0; j < P.d; ++j) {
+        HIPCHK(c, launch_series_stats(T + (size_t)j * ldT, region(j) + L.o_T, L.sT, c->stream));
+        HIPCHK(c, hipMemcpyAsync(&misc[(size_t)j * 4], stats_misc(region(j) + L.o_T, L.sT), 4 * sizeof(double),
+                                 hipMemcpyDeviceToHost, c->stream));
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (int j = 0; j < P.d; ++j)
+        if (misc[(size_t)j * 4 + 2] != 0.0) return fail(c, PST_EINVAL, "coordinate %d holds a non-finite value", j);
+    ProfileJob jobs[kMaxJobs];
+    for (int j = 0; j < P.d; ++j) {
+        unsigned *dm = (unsigned *)(region(j) + L.o_dmax);
+        HIPCHK(c, launch_fill_u32(dm, 1, 0u, c->stream));
+        jobs[j] = job_for(L, region(j), (float *)(region(j) + L.o_D), L.Nm, dm);
+        jobs[j].rw = (float *)(ws + P.o_rw);
+        jobs[j].grid = P.grid;
+        jobs[j].anchor_every = c->opt_anchor;
+    }
+    uint32_t *counter = (uint32_t *)(ws + P.o_counter);
+    HIPCHK(c, launch_fill_u32(counter, 1, 0u, c->stream));
+    HIPCHK(c, profile_prepare(L.w));
+    if (c->timing) HIPCHK(c, hipEventRecord(c->ev0, c->stream));
+    HIPCHK(c, launch_profile_batch(jobs, P.d, P.grid, counter, c->stream));
+    if (c->timing) {
+        HIPCHK(c, hipEventRecord(c->ev1, c->stream));
+        c->timed = true;
+    }
+    for (int j = 0; j < P.d; ++j) {
+        GreedyJob g = greedy_for(L, region(j), (const float *)(region(j) + L.o_D), L.Nm);
+        g.owner = owner ? owner + (size_t)j * L.Nm : nullptr;
+        g.profiles = nullptr;
+        HIPCHK(c, launch_greedy(g, c->stream));
+        HIPCHK(c, launch_owner(g, c->stream));
+    }
+    for (int j = 0; j < P.d; ++j) {
+        const int rc = collect_records(c, L, region(j), out + (size_t)j * L.K, dmax_host ? dmax_host + j : nullptr,
+                                       nullptr);
+        if (rc) return rc;
+    }
+    return PST_OK;
+}
 
 // ---------------------------------------------------------------- length sweep
 // All candidate lengths of eq. 18 in one persistent profile launch, the greedy
@@ -758,6 +832,27 @@ int pst_snippets(pst_ctx *ctx, const double *T_dev, int64_t n, int32_t m, int32_
     char *ws = (char *)ws_dev;
     if ((rc = snippets_device(ctx, T_dev, L, ws, owner_dev, profiles_dev, false))) return rc;
     return collect_records(ctx, L, ws, out_host, dmax_host, nullptr);
+}
+
+size_t pst_snippets_multi_workspace_bytes(int32_t d, int64_t n, int32_t m, int32_t l, int32_t K) {
+    MultiPlan P;
+    if (plan_multi(nullptr, d, n, m, l, 0, K, &P) != PST_OK) return 0;
+    return P.total;
+}
+
+int pst_snippets_multi(pst_ctx *ctx, const double *T_dev, int32_t d, int64_t ld, int64_t n, int32_t m,
+                       int32_t l, int32_t k, int32_t K, pst_snippet *out_host, int32_t *owner_dev,
+                       float *dmax_host, void *ws_dev, size_t ws_bytes) {
+    int rc = begin(ctx);
+    if (rc) return rc;
+    MultiPlan P;
+    if ((rc = plan_multi(ctx, d, n, m, l, k, K, &P))) return rc;
+    if (!T_dev || !out_host) return fail(ctx, PST_EINVAL, "null pointer argument");
+    if (ld < n) return fail(ctx, PST_EINVAL, "ld (%lld) < n (%lld)", (long long)ld, (long long)n);
+    if (!ws_dev) return fail(ctx, PST_EINVAL, "workspace is NULL");
+    if (((uintptr_t)ws_dev & 255) != 0) return fail(ctx, PST_EINVAL, "workspace must be 256-byte aligned");
+    if (ws_bytes < P.total) return fail(ctx, PST_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, P.total);
+    return run_multi(ctx, P, T_dev, ld, (char *)ws_dev, out_host, owner_dev, dmax_host);
 }
 
 int pst_select_length(pst_ctx *ctx, const double *T_dev, int64_t n, const int32_t *m_list,

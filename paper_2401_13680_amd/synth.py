@@ -75,6 +75,45 @@ def regime_series(n: int, seed: int, shapes=SHAPES5, len_range=(2000, 8000),
     return Series(x, lab, tuple(shapes))
 
 
+@dataclass
+class MultiSeries:
+    x: np.ndarray          # float64[d, n], coordinate j in row j
+    labels: np.ndarray     # int32[n], regime class per point (shared by all coordinates)
+
+
+def multivariate_series(n: int, d: int, seed: int, shapes=SHAPES5, len_range=(2000, 8000),
+                        amp_range=(0.5, 2.0), period_range=(20, 200), noise=0.1) -> MultiSeries:
+    """d coordinates switching regime at the same points (one activity seen by
+    d sensors): a regime of class c is drawn in coordinate j with the shape
+    perm_j[c], its own period and amplitude, plus N(0, noise) per coordinate.
+    Consecutive regimes have different classes."""
+    rng = np.random.default_rng(seed)
+    C = len(shapes)
+    perms = [rng.permutation(C) for _ in range(d)]
+    x = np.empty((d, n), dtype=np.float64)
+    lab = np.empty(n, dtype=np.int32)
+    pos, prev = 0, -1
+    level = np.zeros(d)
+    while pos < n:
+        L = min(int(rng.integers(len_range[0], len_range[1] + 1)), n - pos)
+        c = int(rng.integers(0, C))
+        if c == prev:
+            c = (c + 1 + int(rng.integers(0, C - 1))) % C
+        t = np.arange(L, dtype=np.float64)
+        for j in range(d):
+            kind = shapes[perms[j][c]]
+            period = float(rng.integers(period_range[0], period_range[1] + 1))
+            amp = float(rng.uniform(amp_range[0], amp_range[1]))
+            seg = _shape(kind, t, period, amp, rng, level[j])
+            x[j, pos:pos + L] = seg
+            level[j] = float(seg[-1]) if kind == "walk" else 0.0
+        lab[pos:pos + L] = c
+        pos += L
+        prev = c
+    x += rng.normal(0.0, noise, size=(d, n))
+    return MultiSeries(x, lab)
+
+
 def four_regimes(seed: int = 1) -> Series:
     """n=2000: sine P=50, square P=40, sawtooth P=60, random walk sigma 0.1,
     500 points each, plus N(0, 0.05) noise."""
@@ -145,6 +184,7 @@ WORKLOADS = {
     "regimes5_n100000": dict(n=100_000, m=256, l=128, K=4),
     "regimes6_n250000_sweep": dict(n=250_000, m_list=list(range(64, 513, 32)), K=6),
     "walk_n1000000": dict(n=1_000_000, m=512, l=256, K=4),
+    "multi4_n100000": dict(n=100_000, d=4, m=256, l=128, K=4),
 }
 
 
@@ -162,6 +202,8 @@ def workload_series(name: str) -> np.ndarray:
         return regime_series(250_000, 3, SHAPES6).x
     if name == "walk_n1000000":
         return long_walk(1_000_000, 4).x
+    if name == "multi4_n100000":
+        return multivariate_series(100_000, 4, 6).x
     raise KeyError(name)
 
 
