@@ -163,6 +163,64 @@ def multi_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def schedule_bench(args):
+    """Scheduling of section 4.2 on measured run times: a polynomial model fitted
+    on plain per-length runs of three training series predicts the run times of
+    the 15 lengths of the sweep workload (held out); the lengths are then spread
+    over P workers by Karmarkar-Karp on the predictions, and each worker's
+    measured load is compared with contiguous and round-robin splits."""
+    import numpy as np
+    import torch
+
+    from paper_2401_13680_amd import api, synth
+
+    K = 4
+
+    def run_ms(T, m):
+        api.snippets(T, m, m // 2, K)
+        torch.cuda.synchronize()
+        best = 1e30
+        for _ in range(max(args.steps, 1)):
+            t0 = time.perf_counter()
+            api.snippets(T, m, m // 2, K)
+            torch.cuda.synchronize()
+            best = min(best, (time.perf_counter() - t0) * 1e3)
+        return best
+
+    train = []
+    for n, seed in ((60_000, 31), (120_000, 32), (180_000, 33)):
+        T = torch.from_numpy(synth.regime_series(n, seed, synth.SHAPES6).x).cuda()
+        for m in range(64, 513, 64):
+            train.append((n, m, m // 2, run_ms(T, m)))
+    n = 250_000
+    ms_list = list(range(64, 513, 32))
+    T = torch.from_numpy(synth.workload_series("regimes6_n250000_sweep")).cuda()
+    actual = [run_ms(T, m) for m in ms_list]
+    out = dict(workload="schedule_regimes6_n250000", train_runs=len(train), held_out=len(ms_list), models={})
+    for D in (1, 2, 3):
+        M = api.RuntimeModel(D)
+        for r in train:
+            M.observe(*r)
+        M.fit()
+        pred = [M.predict(n, m, m // 2) for m in ms_list]
+        rel = [abs(p - a) / a for p, a in zip(pred, actual)]
+        splits = {}
+        for P in (2, 4, 8):
+            part, _ = api.partition_lengths(M, n, ms_list, P)
+            def imb(assign):
+                loads = [sum(a for a, q in zip(actual, assign) if q == j) for j in range(P)]
+                return max(loads) / (sum(loads) / P)
+            contiguous = [min(i * P // len(ms_list), P - 1) for i in range(len(ms_list))]
+            round_robin = [i % P for i in range(len(ms_list))]
+            splits[f"P{P}"] = dict(kk=round(imb(part), 4), contiguous=round(imb(contiguous), 4),
+                                   round_robin=round(imb(round_robin), 4))
+        out["models"][f"degree{D}"] = dict(mean_rel_err=round(float(np.mean(rel)), 4),
+                                           max_rel_err=round(float(np.max(rel)), 4),
+                                           max_load_over_mean=splits)
+    out["actual_ms"] = [round(a, 3) for a in actual]
+    print(json.dumps(out), flush=True)
+
+
 def serve_bench(args):
     """Serving: Poisson arrivals (20 / s) of regime-switching series with n
     log-uniform in [1e4, 5e5], m in {64, .., 1024}, l = m/2, K in 3..5."""
@@ -224,7 +282,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="regimes5_n100000",
-                    choices=["regimes5_n100000", "sweep", "serve", "multi"])
+                    choices=["regimes5_n100000", "sweep", "serve", "multi", "schedule"])
     ap.add_argument("--requests", type=int, default=40, help="serve: number of requests")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="end with one 1 GiB device copy (reference for FETCH_SIZE / WRITE_SIZE counters)")
@@ -238,6 +296,8 @@ def main():
         return serve_bench(args)
     if args.workload == "multi":
         return multi_bench(args)
+    if args.workload == "schedule":
+        return schedule_bench(args)
 
     import numpy as np
     import torch

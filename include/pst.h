@@ -145,6 +145,46 @@ int pst_select_length(pst_ctx *ctx, const double *T_dev, int64_t n,
                       pst_snippet *out_host, float *profiles_dev, int32_t *owner_dev,
                       void *ws_dev, size_t ws_bytes);
 
+/* ---- Scheduling (section 4.2) ----
+ * Run times predicted by polynomial regression on earlier runs, and the
+ * Karmarkar-Karp partition that spreads candidate lengths over workers with
+ * balanced predicted load.  Host-only: no device, no context.
+ *
+ * A model is a polynomial of total degree `degree` (1..4) in three scaled
+ * sizes of a run: u = floor(n/m)/1e3 (segments), w = (m-l+1)/1e2 (window
+ * width), v = (n-l+1)/1e5 (subsequences); the distance-matrix cell count is
+ * proportional to u*w*v.  Monomials u^a w^b v^c in graded order: total degree
+ * t = 0..degree, a from t down to 0, b from t-a down to 0.
+ * pst_model_fit minimises the relative squared error sum ((p_i - ms_i)/ms_i)^2
+ * plus a ridge of 1e-10 times the mean squared column norm (so that fewer
+ * runs than monomials still determine it), by Householder QR.
+ * Errors: PST_EINVAL for invalid sizes, a non-positive or non-finite time, a
+ * degree outside 1..4; PST_ENOTREADY before the first observation / fit. */
+typedef struct pst_model pst_model;
+int  pst_model_create(pst_model **out, int32_t degree);
+void pst_model_destroy(pst_model *model);
+int  pst_model_observe(pst_model *model, int64_t n, int32_t m, int32_t l, double ms);
+int  pst_model_fit(pst_model *model);
+/* coef_out: up to cap coefficients in monomial order; num_out: their count */
+int  pst_model_coefficients(const pst_model *model, double *coef_out, int32_t cap, int32_t *num_out);
+int  pst_model_predict(const pst_model *model, int64_t n, int32_t m, int32_t l, double *ms_out);
+/* k-way largest differencing of count non-negative costs into `parts`
+ * (1..4096) parts: every item starts as a parts-tuple (cost, 0, .., 0); the two
+ * tuples of largest spread (max - min; ties to the older tuple, items being
+ * older than merges and in input order) are merged slot by slot, largest slot
+ * of the first with smallest of the second, and the merged slots re-sorted
+ * largest first (stable), until one tuple is left.  part_out[i]: the part of
+ * item i (parts numbered by load, largest first); load_out[parts]: each part's
+ * summed cost.  PST_EINVAL for a negative or non-finite cost. */
+int  pst_partition_kk(const double *cost, int32_t count, int32_t parts, int32_t *part_out,
+                      double *load_out);
+/* The candidate lengths of eq. 18 (l_list NULL: l = m/2) spread over `parts`
+ * workers by the model's predicted run times on a series of length n
+ * (negative predictions count as 0). */
+int  pst_partition_lengths(const pst_model *model, int64_t n, const int32_t *m_list,
+                           const int32_t *l_list, int32_t num_m, int32_t parts,
+                           int32_t *part_out, double *load_out);
+
 /* ---- Serving ----
  * A server admits requests (one series each, with its own n, m, l, K) as
  * device memory and slots free up, runs each admitted request's whole

@@ -70,6 +70,15 @@ def load():
         "pst_snippets_multi_workspace_bytes": (c_size_t, [c_int32, c_int64, c_int32, c_int32, c_int32]),
         "pst_snippets_multi": (c_int, [P, P, c_int32, c_int64, c_int64, c_int32, c_int32, c_int32, c_int32,
                                        POINTER(Snippet), P, POINTER(c_float), P, c_size_t]),
+        "pst_model_create": (c_int, [POINTER(P), c_int32]),
+        "pst_model_destroy": (None, [P]),
+        "pst_model_observe": (c_int, [P, c_int64, c_int32, c_int32, c_double]),
+        "pst_model_fit": (c_int, [P]),
+        "pst_model_coefficients": (c_int, [P, POINTER(c_double), c_int32, POINTER(c_int32)]),
+        "pst_model_predict": (c_int, [P, c_int64, c_int32, c_int32, POINTER(c_double)]),
+        "pst_partition_kk": (c_int, [POINTER(c_double), c_int32, c_int32, POINTER(c_int32), POINTER(c_double)]),
+        "pst_partition_lengths": (c_int, [P, c_int64, POINTER(c_int32), POINTER(c_int32), c_int32, c_int32,
+                                          POINTER(c_int32), POINTER(c_double)]),
         "pst_set_timing": (c_int, [P, c_int]),
         "pst_set_option": (c_int, [P, c_int, c_int64]),
         "pst_server_create": (c_int, [POINTER(P), c_int, c_size_t, c_int32]),

@@ -278,3 +278,81 @@ class Server:
 
 def request_bytes(n: int, m: int, l: int, K: int) -> int:
     return int(_lib.load().pst_request_bytes(n, m, l, K))
+
+
+class RuntimeModel:
+    """Polynomial run-time model of section 4.2 (pst_model_*): observe earlier
+    runs (n, m, l, ms), fit, predict.  Host-only."""
+
+    def __init__(self, degree: int = 2):
+        self.L = _lib.load()
+        h = c_void_p()
+        rc = self.L.pst_model_create(byref(h), degree)
+        if rc != 0:
+            raise PstError(rc, f"pst_model_create(degree={degree}) failed")
+        self.h = h
+        self.degree = degree
+
+    def observe(self, n: int, m: int, l: int, ms: float):
+        rc = self.L.pst_model_observe(self.h, n, m, l, float(ms))
+        if rc != 0:
+            raise PstError(rc, f"bad observation n={n} m={m} l={l} ms={ms}")
+
+    def fit(self):
+        rc = self.L.pst_model_fit(self.h)
+        if rc != 0:
+            raise PstError(rc, "fit failed")
+
+    def coefficients(self):
+        num = c_int32()
+        rc = self.L.pst_model_coefficients(self.h, None, 0, byref(num))
+        if rc != 0:
+            raise PstError(rc, "model not fitted")
+        out = (c_double * num.value)()
+        self.L.pst_model_coefficients(self.h, out, num.value, byref(num))
+        return list(out)
+
+    def predict(self, n: int, m: int, l: int) -> float:
+        out = c_double()
+        rc = self.L.pst_model_predict(self.h, n, m, l, byref(out))
+        if rc != 0:
+            raise PstError(rc, f"cannot predict n={n} m={m} l={l}")
+        return out.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.pst_model_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def partition_kk(costs, parts: int):
+    """Karmarkar-Karp k-way partition (pst_partition_kk): (part of each item, load of each part)."""
+    L = _lib.load()
+    cnt = len(costs)
+    c = (c_double * max(cnt, 1))(*[float(x) for x in costs])
+    po = (c_int32 * max(cnt, 1))()
+    lo = (c_double * parts)()
+    rc = L.pst_partition_kk(c, cnt, parts, po, lo)
+    if rc != 0:
+        raise PstError(rc, "pst_partition_kk failed")
+    return list(po)[:cnt], list(lo)
+
+
+def partition_lengths(model: RuntimeModel, n: int, m_list, parts: int, l_list=None):
+    """Candidate lengths spread over `parts` workers by predicted run time."""
+    L = _lib.load()
+    k = len(m_list)
+    ms = (c_int32 * k)(*m_list)
+    ls = (c_int32 * k)(*l_list) if l_list is not None else None
+    po = (c_int32 * k)()
+    lo = (c_double * parts)()
+    rc = L.pst_partition_lengths(model.h, n, ms, ls, k, parts, po, lo)
+    if rc != 0:
+        raise PstError(rc, "pst_partition_lengths failed")
+    return list(po), list(lo)

@@ -11,7 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpst.so")
-SOURCES = ["pst_stats.hip", "pst_profile.hip", "pst_greedy.hip", "pst_label.hip", "pst_api.cpp"]
+SOURCES = ["pst_stats.hip", "pst_profile.hip", "pst_greedy.hip", "pst_label.hip", "pst_api.cpp", "pst_sched.cpp"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
