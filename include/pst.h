@@ -214,6 +214,20 @@ int pst_poll(pst_server *server, uint64_t ticket, pst_snippet *out_host, int32_t
 /* Wait until no request is queued or running: PST_OK, or PST_ENOTREADY at the timeout. */
 int pst_server_drain(pst_server *server, int32_t timeout_ms);
 /* Completed requests, their distance-matrix cells, running requests, bytes held. */
+/* Admission order (section 4.2's run-time prediction applied to one GPU's
+ * queue).  PST_POLICY_ARRIVAL (the default): first fit in arrival order.
+ * PST_POLICY_SHORTEST_PREDICTED: first fit, scanning the waiting requests by
+ * predicted run time, shortest first (equal predictions in arrival order).
+ * The prediction comes from the server's own degree-2 model (a copy of `seed`
+ * when given, which the caller keeps ownership of), extended with the device
+ * time of every completed request (from its first to its last operation on
+ * its stream, so overlap with other requests is included) and refitted after
+ * every fourth; without a fitted model a request's cell count is its
+ * prediction.  Shortest-first lowers typical latency; a long request can
+ * wait behind shorter ones that keep arriving.  PST_EINVAL for an unknown
+ * policy. */
+enum { PST_POLICY_ARRIVAL = 0, PST_POLICY_SHORTEST_PREDICTED = 1 };
+int pst_server_set_policy(pst_server *server, int32_t policy, const pst_model *seed);
 int pst_server_stats(pst_server *server, uint64_t *completed, double *cells, int32_t *active,
                      size_t *bytes_in_use);
 /* Host-only simulation of the admission policy (no device use), for tests:
@@ -223,6 +237,12 @@ int pst_server_stats(pst_server *server, uint64_t *completed, double *cells, int
  * the budget. */
 int pst_admission_simulate(size_t budget, int32_t slots, int32_t count, const size_t *bytes,
                            const double *arrive_ms, const double *service_ms, double *start_ms);
+/* As pst_admission_simulate, with the waiting requests scanned by ascending
+ * priority[i] (ties in arrival order) instead of arrival order; priority NULL
+ * gives arrival order. */
+int pst_admission_simulate_ordered(size_t budget, int32_t slots, int32_t count, const size_t *bytes,
+                                   const double *arrive_ms, const double *service_ms,
+                                   const double *priority, double *start_ms);
 
 /* Labelling score (the per-element F1 of section 5.2's accuracy experiment).
  * owner_dev: int32[n-m+1], the greedy rank (0 .. K-1) of each window's nearest

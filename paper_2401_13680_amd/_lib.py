@@ -92,6 +92,10 @@ def load():
                                      POINTER(c_size_t)]),
         "pst_admission_simulate": (c_int, [c_size_t, c_int32, c_int32, POINTER(c_size_t),
                                            POINTER(c_double), POINTER(c_double), POINTER(c_double)]),
+        "pst_admission_simulate_ordered": (c_int, [c_size_t, c_int32, c_int32, POINTER(c_size_t),
+                                                   POINTER(c_double), POINTER(c_double), POINTER(c_double),
+                                                   POINTER(c_double)]),
+        "pst_server_set_policy": (c_int, [P, c_int32, P]),
         "pst_last_profile_ms": (c_int, [P, POINTER(c_float)]),
         "pst_label_workspace_bytes": (c_size_t, [c_int32, c_int32]),
         "pst_label_f1": (c_int, [P, P, c_int64, c_int32, c_int32, P, c_int32, POINTER(c_int32),

@@ -259,6 +259,15 @@ class Server:
         if rc != 0:
             raise PstError(rc, self.L.pst_server_last_error(self.h).decode())
 
+    ARRIVAL, SHORTEST_PREDICTED = 0, 1
+
+    def set_policy(self, policy: int, seed: "RuntimeModel | None" = None):
+        """Admission order: Server.ARRIVAL or Server.SHORTEST_PREDICTED (run
+        times from a copy of `seed`, grown with every completed request)."""
+        rc = self.L.pst_server_set_policy(self.h, policy, seed.h if seed is not None else None)
+        if rc != 0:
+            raise PstError(rc, f"bad policy {policy}")
+
     def stats(self):
         c, cells, a, b = ctypes.c_uint64(), c_double(), c_int32(), ctypes.c_size_t()
         self.L.pst_server_stats(self.h, byref(c), byref(cells), byref(a), byref(b))

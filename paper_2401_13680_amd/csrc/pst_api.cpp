@@ -21,6 +21,7 @@
 
 #include "../../include/pst.h"
 #include "pst_internal.h"
+#include "pst_sched.h"
 
 struct GraphEntry {
     std::vector<int64_t> key;

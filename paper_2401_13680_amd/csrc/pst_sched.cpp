@@ -9,13 +9,7 @@
 #include <vector>
 
 #include "../../include/pst.h"
-
-struct pst_model {
-    int degree;
-    std::vector<double> u, w, v, ms;   // observations (scaled sizes) and run times
-    std::vector<double> coef;          // one per monomial, graded order
-    bool fitted = false;
-};
+#include "pst_sched.h"
 
 namespace {
 
