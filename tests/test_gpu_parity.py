@@ -55,6 +55,14 @@ CASES = [
     ("n_not_multiple", lambda: synth.regime_series(2050, 6, len_range=(200, 600)).x, 64, 32, 0),
     ("wide_w", lambda: synth.regime_series(3000, 7, len_range=(300, 900)).x, 256, 32, 0),
     ("random_walk", lambda: np.cumsum(np.random.default_rng(8).normal(size=2500)) + 500.0, 50, 25, 0),
+    # every workgroup shape of the profile kernel: 256 threads with 6 diagonals
+    # per thread; 512 threads with 256 blocks per tile, 5 or 6 diagonals, 4 or
+    # 8 rows per chunk, 1984 or 992 windows per sub-tile; the largest w
+    ("w160_v6", lambda: synth.regime_series(3000, 22, len_range=(300, 900)).x, 320, 161, 0),
+    ("w270", lambda: synth.regime_series(3200, 23, len_range=(300, 900)).x, 400, 131, 0),
+    ("w400", lambda: synth.regime_series(3000, 24, len_range=(300, 900)).x, 500, 101, 0),
+    ("w700", lambda: synth.regime_series(3000, 25, len_range=(300, 900)).x, 800, 101, 0),
+    ("w_max_1025", lambda: synth.regime_series(2500, 26, len_range=(300, 900)).x, 1100, 76, 0),
 ]
 
 
