@@ -221,6 +221,45 @@ def schedule_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def blocked_bench(args):
+    """Bounded memory: a 10^6-point five-shape series, m=256, l=128, K=4 (profile
+    set 15.6 GB), in core against pst_snippets_blocked with a 4 GiB workspace."""
+    import torch
+
+    from paper_2401_13680_amd import api, synth
+
+    n, m, l, K = 1_000_000, 256, 128, 4
+    T = torch.from_numpy(synth.regime_series(n, 8, synth.SHAPES5).x).cuda()
+    cells = (n // m) * (m - l + 1) * (n - l + 1)
+    res = {}
+    for mode in ("in_core", "blocked"):
+        def step():
+            if mode == "in_core":
+                return api.snippets(T, m, l, K, owner=True)
+            return api.snippets_blocked(T, m, l, K, budget_bytes=4 << 30, owner=True)
+        step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(max(args.steps, 1)):
+            r = step()
+        torch.cuda.synchronize()
+        res[mode] = ((time.perf_counter() - t0) / max(args.steps, 1), r)
+    ctx = api.context(0)
+    ws_in = int(ctx.L.pst_workspace_bytes(n, m, l, K))
+    rb = res["blocked"][1]
+    out = dict(workload="blocked_regimes5_n1000000", n=n, m=m, l=l, K=K, cells=cells,
+               in_core=dict(seconds=round(res["in_core"][0], 4), workspace_bytes=ws_in,
+                            cells_per_s=cells / res["in_core"][0]),
+               blocked=dict(seconds=round(res["blocked"][0], 4), workspace_bytes=rb["workspace_bytes"],
+                            seg_block=rb["seg_block"], segments=n // m,
+                            cells_per_s_of_the_problem=cells / res["blocked"][0]),
+               time_ratio=res["blocked"][0] / res["in_core"][0],
+               memory_ratio=ws_in / rb["workspace_bytes"],
+               identical=(rb["records"] == res["in_core"][1]["records"]
+                          and bool(torch.equal(rb["owner"], res["in_core"][1]["owner"]))))
+    print(json.dumps(out), flush=True)
+
+
 def serve_bench(args):
     """Serving: Poisson arrivals (20 / s) of regime-switching series with n
     log-uniform in [1e4, 5e5], m in {64, .., 1024}, l = m/2, K in 3..5."""
@@ -311,7 +350,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="regimes5_n100000",
-                    choices=["regimes5_n100000", "sweep", "serve", "multi", "schedule"])
+                    choices=["regimes5_n100000", "sweep", "serve", "multi", "schedule", "blocked"])
     ap.add_argument("--requests", type=int, default=40, help="serve: number of requests")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="end with one 1 GiB device copy (reference for FETCH_SIZE / WRITE_SIZE counters)")
@@ -327,6 +366,8 @@ def main():
         return multi_bench(args)
     if args.workload == "schedule":
         return schedule_bench(args)
+    if args.workload == "blocked":
+        return blocked_bench(args)
 
     import numpy as np
     import torch

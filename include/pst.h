@@ -113,6 +113,26 @@ int pst_snippets(pst_ctx *ctx, const double *T_dev, int64_t n, int32_t m, int32_
                  int32_t k, int32_t K, pst_snippet *out_host, float *profiles_dev,
                  int32_t *owner_dev, float *dmax_host, void *ws_dev, size_t ws_bytes);
 
+/* Bounded device memory (series whose profile set D does not fit): the same
+ * result as pst_snippets without ever holding D whole.  Every greedy round
+ * recomputes D in blocks of seg_block segments (1 <= seg_block <= n/m),
+ * reduces each block to the segments' areas against the current curve (eq. 17)
+ * and drops it; the picked segment's profile is recomputed alone and kept.
+ * Device memory grows with seg_block * (n-m+1) + K * (n-m+1) floats instead
+ * of (n/m) * (n-m+1); the profile work is K + 1 times that of pst_snippets.
+ * Records, profiles_dev, owner_dev and dmax_host are bit-identical to
+ * pst_snippets'.  The workspace must hold
+ * pst_snippets_blocked_workspace_bytes(n, m, l, K, seg_block) bytes (0 for
+ * invalid sizes); pst_snippets_blocked_max_block gives the largest seg_block
+ * whose workspace fits budget_bytes (0 if none).  Errors as pst_snippets,
+ * plus PST_EINVAL for seg_block outside [1, n/m]. */
+size_t pst_snippets_blocked_workspace_bytes(int64_t n, int32_t m, int32_t l, int32_t K, int32_t seg_block);
+int32_t pst_snippets_blocked_max_block(int64_t n, int32_t m, int32_t l, int32_t K, size_t budget_bytes);
+int pst_snippets_blocked(pst_ctx *ctx, const double *T_dev, int64_t n, int32_t m, int32_t l,
+                         int32_t k, int32_t K, int32_t seg_block, pst_snippet *out_host,
+                         float *profiles_dev, int32_t *owner_dev, float *dmax_host,
+                         void *ws_dev, size_t ws_bytes);
+
 /* Multivariate series (eqs. 1-2): d coordinates of length n, coordinate j
  * at T_dev + j*ld (float64, ld >= n).  Section 3.2 runs the snippet search on
  * each coordinate independently; here every coordinate's profile set runs in

@@ -131,6 +131,33 @@ def snippets(T, m: int, l: int, K: int, k: int = 0, profiles: bool = False, owne
     return dict(records=_records(recs, K), profiles=prof, owner=own, dmax=float(dmax.value))
 
 
+def snippets_blocked(T, m: int, l: int, K: int, seg_block: int = 0, k: int = 0, budget_bytes: int = 0,
+                     profiles: bool = False, owner: bool = False, ctx: Context | None = None):
+    """pst_snippets' result without holding the profile set whole: D is
+    recomputed every greedy round in blocks of seg_block segments (or the
+    largest block whose workspace fits budget_bytes)."""
+    T = _series(T)
+    ctx = ctx or context(T.device.index)
+    n = T.numel()
+    if seg_block <= 0:
+        seg_block = int(ctx.L.pst_snippets_blocked_max_block(n, m, l, K, budget_bytes))
+        if seg_block <= 0:
+            raise PstError(-1, f"no block fits {budget_bytes} bytes (n={n} m={m} l={l} K={K})")
+    nb = ctx.L.pst_snippets_blocked_workspace_bytes(n, m, l, K, seg_block)
+    if nb == 0:
+        raise PstError(-1, f"invalid sizes n={n} m={m} l={l} K={K} seg_block={seg_block}")
+    Nm = n - m + 1
+    prof = torch.empty((K, Nm), dtype=torch.float32, device=T.device) if profiles else None
+    own = torch.empty(Nm, dtype=torch.int32, device=T.device) if owner else None
+    recs = (Snippet * K)()
+    dmax = c_float()
+    ws = ctx.workspace(nb)
+    ctx.check(ctx.L.pst_snippets_blocked(ctx.h, _ptr(T), n, m, l, k, K, seg_block, recs, _ptr(prof), _ptr(own),
+                                          byref(dmax), _ptr(ws), ws.numel()))
+    return dict(records=_records(recs, K), profiles=prof, owner=own, dmax=float(dmax.value),
+                seg_block=seg_block, workspace_bytes=nb)
+
+
 def snippets_multi(X, m: int, l: int, K: int, k: int = 0, owner: bool = False, ctx: Context | None = None):
     """Snippets of every coordinate of a multivariate series X (d x n, float64,
     on the GPU), the coordinates searched independently (section 3.2) in one

@@ -331,6 +331,140 @@ int run_multi(pst_ctx *c, const MultiPlan &P, const double *T, int64_t ldT, char
     return PST_OK;
 }
 
+// ---------------------------------------------------------------- bounded memory
+// The profile set D never held whole: every greedy round recomputes D in
+// blocks of B segments, reduces each block to the segments' areas against the
+// current curve M (eq. 17) and drops it; the picked segment's profile is then
+// recomputed alone, kept (K rows) and folded into M.  Device memory is
+// O(B (n-m+1) + K (n-m+1)) instead of O(nseg (n-m+1)), for K+1 times the
+// profile work.  A cell's arithmetic does not depend on the block it is
+// computed in, so every step sees the same values as the in-core path.
+struct BlockedLayout {
+    Layout L;            // sizes (its D and scratch regions are not used)
+    int32_t B = 0, grid = 0;
+    size_t o_T, o_Dblk, o_P, o_M, o_part, o_pick, o_area, o_chosen, o_count, o_iota, o_dmax, o_rw, total;
+};
+
+int plan_blocked(pst_ctx *c, int64_t n, int32_t m, int32_t l, int32_t k, int32_t K, int32_t B, BlockedLayout *P) {
+    if (K < 1) return fail(c, PST_EINVAL, "need K >= 1 (K=%d)", K);
+    int rc = plan(c, n, m, l, k, K, &P->L, false);
+    if (rc) return rc;
+    const Layout &L = P->L;
+    if (B < 1 || B > L.nseg) return fail(c, PST_EINVAL, "need 1 <= seg_block <= n/m (seg_block=%d, n/m=%d)", B, L.nseg);
+    P->B = B;
+    P->grid = profile_grid(L.ntile * (int64_t)B, L.w);
+    size_t o = 0;
+    P->o_T = o;      o = al(o + L.sT.total);
+    P->o_Dblk = o;   o = al(o + sizeof(float) * (size_t)B * L.Nm);
+    P->o_P = o;      o = al(o + sizeof(float) * (size_t)K * L.Nm);
+    P->o_M = o;      o = al(o + sizeof(float) * L.Nm);
+    P->o_part = o;   o = al(o + sizeof(double) * (size_t)L.nseg * L.nblk);
+    P->o_pick = o;   o = al(o + sizeof(int32_t) * K);
+    P->o_area = o;   o = al(o + sizeof(double) * K);
+    P->o_chosen = o; o = al(o + (size_t)L.nseg);
+    P->o_count = o;  o = al(o + sizeof(int32_t) * K);
+    P->o_iota = o;   o = al(o + sizeof(int32_t) * K);
+    P->o_dmax = o;   o = al(o + 256);
+    P->o_rw = o;     o = al(o + sizeof(float) * profile_scratch_floats(P->grid, L.w));
+    P->total = o;
+    return PST_OK;
+}
+
+// Statistics of the rows of segments s0 .. : the series' own statistics
+// shifted by s0 segments.
+Stats rows_from(Stats s, int64_t off) {
+    s.xc += off;
+    s.mu += off;
+    s.inv += off;
+    s.h += off;
+    s.df += off;
+    s.dg += off;
+    return s;
+}
+
+int run_blocked(pst_ctx *c, const BlockedLayout &P, const double *T, char *ws, pst_snippet *out, float *profiles,
+                int32_t *owner, float *dmax_host) {
+    const Layout &L = P.L;
+    int rc = series_stats(c, T, ws + P.o_T, L.sT, "T");
+    if (rc) return rc;
+    const Stats st = stats_view(ws + P.o_T, L.sT);
+    unsigned *dmax = (unsigned *)(ws + P.o_dmax);
+    HIPCHK(c, launch_fill_u32(dmax, 1, 0u, c->stream));
+    std::vector<int32_t> iota(L.K);
+    for (int p = 0; p < L.K; ++p) iota[p] = p;
+    HIPCHK(c, hipMemcpyAsync(ws + P.o_iota, iota.data(), sizeof(int32_t) * L.K, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, profile_prepare(L.w));
+    // greedy state for the whole set; D is only ever a block or the kept rows
+    GreedyJob G{};
+    G.ld = L.Nm;
+    G.Nm = L.Nm;
+    G.nseg = L.nseg;
+    G.K = L.K;
+    G.M = (float *)(ws + P.o_M);
+    G.part = (double *)(ws + P.o_part);
+    G.nblk = L.nblk;
+    G.pick = (int32_t *)(ws + P.o_pick);
+    G.area = (double *)(ws + P.o_area);
+    G.chosen = (uint8_t *)(ws + P.o_chosen);
+    G.count = (int32_t *)(ws + P.o_count);
+    G.crit = nullptr;
+    G.nblk2 = 0;
+    float *Dblk = (float *)(ws + P.o_Dblk);
+    float *Prow = (float *)(ws + P.o_P);
+    HIPCHK(c, launch_greedy_init(G, c->stream));
+    ProfileJob base = job_for(L, ws, Dblk, L.Nm, nullptr);
+    base.col = st;
+    base.rw = (float *)(ws + P.o_rw);
+    base.anchor_every = c->opt_anchor;
+    for (int r = 0; r < L.K; ++r) {
+        for (int32_t s0 = 0; s0 < L.nseg; s0 += P.B) {
+            const int32_t nb = std::min(P.B, L.nseg - s0);
+            ProfileJob j = base;
+            j.row = rows_from(st, (int64_t)s0 * L.m);
+            j.nq = nb;
+            j.D = Dblk;
+            j.dmax_bits = r == 0 ? dmax : nullptr;
+            j.grid = profile_grid(L.ntile * (int64_t)nb, L.w);
+            HIPCHK(c, launch_profile_batch(&j, 1, j.grid, nullptr, c->stream));
+            GreedyJob Gb = G;
+            Gb.D = Dblk;
+            Gb.nseg = nb;
+            Gb.part = G.part + (size_t)s0 * L.nblk;
+            Gb.chosen = G.chosen + s0;
+            HIPCHK(c, launch_area_parts(Gb, c->stream));
+        }
+        HIPCHK(c, launch_pick(G, r, c->stream));
+        int32_t pk = 0;
+        HIPCHK(c, hipMemcpyAsync(&pk, G.pick + r, sizeof pk, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        // the picked segment's profile, alone, kept as row r
+        ProfileJob j = base;
+        j.row = rows_from(st, (int64_t)pk * L.m);
+        j.nq = 1;
+        j.D = Prow + (size_t)r * L.Nm;
+        j.dmax_bits = nullptr;
+        j.grid = profile_grid(L.ntile, L.w);
+        HIPCHK(c, launch_profile_batch(&j, 1, j.grid, nullptr, c->stream));
+        GreedyJob Gk = G;
+        Gk.D = Prow;
+        Gk.pick = (int32_t *)(ws + P.o_iota);
+        HIPCHK(c, launch_update_M(Gk, r, c->stream));
+    }
+    // neighbours and counts over the kept rows (row p = the p-th pick)
+    GreedyJob Go = G;
+    Go.D = Prow;
+    Go.pick = (int32_t *)(ws + P.o_iota);
+    Go.owner = owner;
+    Go.profiles = profiles;
+    HIPCHK(c, launch_owner(Go, c->stream));
+    Layout Lr = L;  // collect_records reads picks, areas, counts and max at these offsets
+    Lr.o_pick = P.o_pick;
+    Lr.o_area = P.o_area;
+    Lr.o_count = P.o_count;
+    Lr.o_dmax = P.o_dmax;
+    return collect_records(c, Lr, ws, out, dmax_host, nullptr);
+}
+
 // ---------------------------------------------------------------- length sweep
 // All candidate lengths of eq. 18 in one persistent profile launch, the greedy
 // search / neighbours / criterion of each candidate after it, and a gather of
@@ -833,6 +967,39 @@ int pst_snippets(pst_ctx *ctx, const double *T_dev, int64_t n, int32_t m, int32_
     char *ws = (char *)ws_dev;
     if ((rc = snippets_device(ctx, T_dev, L, ws, owner_dev, profiles_dev, false))) return rc;
     return collect_records(ctx, L, ws, out_host, dmax_host, nullptr);
+}
+
+size_t pst_snippets_blocked_workspace_bytes(int64_t n, int32_t m, int32_t l, int32_t K, int32_t seg_block) {
+    BlockedLayout P;
+    if (plan_blocked(nullptr, n, m, l, 0, K, seg_block, &P) != PST_OK) return 0;
+    return P.total;
+}
+
+int32_t pst_snippets_blocked_max_block(int64_t n, int32_t m, int32_t l, int32_t K, size_t budget_bytes) {
+    Layout L;
+    if (K < 1 || plan(nullptr, n, m, l, 0, K, &L, false) != PST_OK) return 0;
+    // the workspace grows with the block: largest block that fits, by bisection
+    int32_t lo = 0, hi = L.nseg;
+    while (lo < hi) {
+        const int32_t mid = lo + (hi - lo + 1) / 2;
+        if (pst_snippets_blocked_workspace_bytes(n, m, l, K, mid) <= budget_bytes) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+int pst_snippets_blocked(pst_ctx *ctx, const double *T_dev, int64_t n, int32_t m, int32_t l, int32_t k, int32_t K,
+                         int32_t seg_block, pst_snippet *out_host, float *profiles_dev, int32_t *owner_dev,
+                         float *dmax_host, void *ws_dev, size_t ws_bytes) {
+    int rc = begin(ctx);
+    if (rc) return rc;
+    BlockedLayout P;
+    if ((rc = plan_blocked(ctx, n, m, l, k, K, seg_block, &P))) return rc;
+    if (!T_dev || !out_host) return fail(ctx, PST_EINVAL, "null pointer argument");
+    if (!ws_dev) return fail(ctx, PST_EINVAL, "workspace is NULL");
+    if (((uintptr_t)ws_dev & 255) != 0) return fail(ctx, PST_EINVAL, "workspace must be 256-byte aligned");
+    if (ws_bytes < P.total) return fail(ctx, PST_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, P.total);
+    return run_blocked(ctx, P, T_dev, (char *)ws_dev, out_host, profiles_dev, owner_dev, dmax_host);
 }
 
 size_t pst_snippets_multi_workspace_bytes(int32_t d, int64_t n, int32_t m, int32_t l, int32_t K) {

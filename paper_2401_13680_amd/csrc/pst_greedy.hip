@@ -198,6 +198,27 @@ hipError_t launch_greedy(const GreedyJob &g, hipStream_t st) {
     return hipGetLastError();
 }
 
+hipError_t launch_greedy_init(const GreedyJob &g, hipStream_t st) {
+    hipLaunchKernelGGL(k_fill, dim3(grid_for(g.Nm)), dim3(GT), 0, st, g.M, g.Nm, INFINITY);
+    hipLaunchKernelGGL(k_zero_u8, dim3(grid_for(g.nseg)), dim3(GT), 0, st, g.chosen, (int64_t)g.nseg);
+    return hipGetLastError();
+}
+
+hipError_t launch_area_parts(const GreedyJob &g, hipStream_t st) {
+    hipLaunchKernelGGL(k_area_part, dim3(g.nblk, g.nseg), dim3(GT), 0, st, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_pick(const GreedyJob &g, int iter, hipStream_t st) {
+    hipLaunchKernelGGL(k_pick, dim3(1), dim3(1024), 0, st, g, iter);
+    return hipGetLastError();
+}
+
+hipError_t launch_update_M(const GreedyJob &g, int iter, hipStream_t st) {
+    hipLaunchKernelGGL(k_update_M, dim3(grid_for(g.Nm)), dim3(GT), 0, st, g, iter);
+    return hipGetLastError();
+}
+
 hipError_t launch_owner(const GreedyJob &g, hipStream_t st) {
     hipLaunchKernelGGL(k_zero_i32, dim3(grid_for(g.K)), dim3(GT), 0, st, g.count, (int64_t)g.K);
     const size_t lds = g.K <= 1024 ? sizeof(int) * g.K : 0;

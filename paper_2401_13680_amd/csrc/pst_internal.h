@@ -94,6 +94,13 @@ struct GreedyJob {
     int32_t nblk2;
 };
 hipError_t launch_greedy(const GreedyJob &g, hipStream_t st);
+// The greedy search's steps one by one (M = +inf and nothing chosen; the
+// area partials of g.nseg segments of g.D; the pick of round iter; M folded
+// with row g.pick[iter] of g.D), for callers that produce D in pieces.
+hipError_t launch_greedy_init(const GreedyJob &g, hipStream_t st);
+hipError_t launch_area_parts(const GreedyJob &g, hipStream_t st);
+hipError_t launch_pick(const GreedyJob &g, int iter, hipStream_t st);
+hipError_t launch_update_M(const GreedyJob &g, int iter, hipStream_t st);
 // Fill n 32-bit words with v by a kernel (no memset nodes, so it is safe to
 // capture in a graph).
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t st);
