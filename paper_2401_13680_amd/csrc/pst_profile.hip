@@ -53,6 +53,7 @@ namespace pst {
 namespace {
 
 constexpr int G = 31;      // windows per block (odd: conflict-free LDS strides)
+constexpr int kStageIters = 5;   // column-statistics entries per thread per sub-tile, at most
 constexpr int CAP = 28;    // sorted candidate list capacity
 constexpr int NB = 16;     // radix buckets per level
 constexpr int BAND = 8;    // bracket half-width in ranks
@@ -393,6 +394,21 @@ __device__ __forceinline__ int coop_band(const float *ab, int gs, const float *b
     return 1;
 }
 
+// Global-to-LDS copy of n doubles by NT threads, four loads in flight per
+// thread before their stores.
+template <int NT>
+__device__ __forceinline__ void stage_f64(double *dst, const double *src, int n, int t) {
+    constexpr int U = 4;
+    for (int b = t; b < n; b += U * NT) {
+        double v[U];
+#pragma unroll
+        for (int e = 0; e < U; ++e) v[e] = b + e * NT < n ? src[b + e * NT] : 0.0;
+#pragma unroll
+        for (int e = 0; e < U; ++e)
+            if (b + e * NT < n) dst[b + e * NT] = v[e];
+    }
+}
+
 // Centred covariance of row r = rb + i and column C0 + u by a direct FP64 dot
 // product (the anchor of a diagonal).
 __device__ __forceinline__ float anchor_at(const ProfileJob &J, int64_t rb, int i, int64_t C0, int u) {
@@ -547,18 +563,29 @@ __global__ void __launch_bounds__(NT, 2) k_profile(ProfileArgs A) {
             const int64_t C0 = J0 + Js;           // first column (series index)
             const int ldb = M.ldb;
             lds_barrier();  // previous sub-tile done with the shared region
-            for (int u = t; u < CS + V + 2; u += NT) {
+            {
                 // entry u holds column u-1; columns -1 and CS+V (and all past
                 // them, by clamping) read as zeros: df = dg = 0 there, so a
                 // partial diagonal's covariance stays at its anchor until the
-                // diagonal enters the sub-tile
-                float4 c = make_float4(0.0f, 0.0f, 0.0f, 0.5f);
-                if (u >= 1 && u <= CS + V) {
-                    const int64_t cc = C0 + u - 1;
-                    c = make_float4(J.col.inv[cc], J.col.df[cc], J.col.dg[cc], 0.5f - 0.5f * J.col.h[cc]);
+                // diagonal enters the sub-tile.  All of a thread's loads are
+                // issued before its stores (CS + V + 2 <= kStageIters * NT).
+                float4 cv[kStageIters];
+#pragma unroll
+                for (int it = 0; it < kStageIters; ++it) {
+                    const int u = t + it * NT;
+                    float4 c = make_float4(0.0f, 0.0f, 0.0f, 0.5f);
+                    if (u >= 1 && u <= CS + V) {
+                        const int64_t cc = C0 + u - 1;
+                        c = make_float4(J.col.inv[cc], J.col.df[cc], J.col.dg[cc], 0.5f - 0.5f * J.col.h[cc]);
+                    }
+                    cv[it] = c;
                 }
-                M.cst[u] = c;
-                if (u < CS) M.colS[u] = INFINITY;
+#pragma unroll
+                for (int it = 0; it < kStageIters; ++it) {
+                    const int u = t + it * NT;
+                    if (u < CS + V + 2) M.cst[u] = cv[it];
+                    if (u < CS) M.colS[u] = INFINITY;
+                }
             }
 
             // Thread t owns diagonals t*V-off .. t*V-off+V-1, diagonal d the
@@ -584,8 +611,8 @@ __global__ void __launch_bounds__(NT, 2) k_profile(ProfileArgs A) {
             float cov[V];
             if (staged) {
                 double *Xc = (double *)M.buf, *Xr = Xc + ncx;
-                for (int q = t; q < ncx; q += NT) Xc[q] = J.col.xc[C0 + q];
-                for (int q = t; q < nrx; q += NT) Xr[q] = J.row.xc[rb + q];
+                stage_f64<NT>(Xc, J.col.xc + C0, ncx, t);
+                stage_f64<NT>(Xr, J.row.xc + rb, nrx, t);
                 lds_barrier();
                 diag_anchors<V>(cov, Xr, Xc, act, d0, w, l, ndg, J.row.mu + rb, J.col.mu + C0);
             } else {
@@ -918,7 +945,7 @@ bool geometry_ok(int w, const Geo &g) {
     const int nbl = (cws + G - 1) / G;
     const int rpw = g.RCH > g.NT / 64 ? g.RCH / (g.NT / 64) : 1;
     const int lpr = 64 / rpw;
-    return w <= kMaxW && g.V * g.NT >= cws + w - 1 + g.V - 1 && g.SBW <= lpr * G && nbl <= 2 * lpr && nbl <= BMW &&
+    return w <= kMaxW && g.V * g.NT >= cws + w - 1 + g.V - 1 && cws + g.V + 2 <= kStageIters * g.NT && g.SBW <= lpr * G && nbl <= 2 * lpr && nbl <= BMW &&
            4 * lds_floats(w, g) <= (g.NT == 256 ? kLdsTwo : kLdsOne);
 }
 
