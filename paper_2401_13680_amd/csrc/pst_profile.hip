@@ -824,7 +824,17 @@ __global__ void __launch_bounds__(NT, 2) k_profile(ProfileArgs A) {
         //    Windows whose bracket misses are solved by the whole wave together.
         __syncthreads();  // the distance phase is done with LDS; colG is written
         float *colY = M.colY;
-        for (int u = t; u < CWT; u += NT) colY[u] = u < JTe + w - 1 ? colG[u] : INFINITY;
+        for (int u0 = t; u0 < CWT; u0 += 8 * NT) {  // eight loads in flight per thread
+            float cy[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int u = u0 + e * NT;
+                cy[e] = u < JTe + w - 1 ? colG[u] : INFINITY;
+            }
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+                if (u0 + e * NT < CWT) colY[u0 + e * NT] = cy[e];
+        }
         lds_barrier();
         if (t < nA && (t & ~63) * G < JTe) {  // waves with a window in the tile
             uint32_t *L = (uint32_t *)M.lst + t;
