@@ -9,7 +9,13 @@
  *     (section 4.1, eqs. 9-15),
  *   - greedy minimum-area snippet selection with neighbours and frac
  *     (section 3.2, eqs. 5-8; section 4.1, eqs. 16-17),
- *   - the snippet-length criterion over candidate lengths (section 4.2, eq. 18).
+ *   - the snippet-length criterion over candidate lengths (section 4.2, eq. 18),
+ *   - multivariate series, each coordinate searched on its own (eqs. 1-2,
+ *     section 3.2), and the same search in bounded device memory,
+ *   - labelling of the series by its snippets and its per-element F1
+ *     (section 5.2's accuracy measure),
+ *   - run-time prediction and Karmarkar-Karp partitioning of candidate
+ *     lengths (section 4.2; host only), and a request server.
  *
  * Conventions
  *   - Every index is 0-based (the paper is 1-based).  A snippet's index is its
