@@ -139,6 +139,22 @@ int pst_snippets_blocked(pst_ctx *ctx, const double *T_dev, int64_t n, int32_t m
                          float *profiles_dev, int32_t *owner_dev, float *dmax_host,
                          void *ws_dev, size_t ws_bytes);
 
+/* eq. 18 in bounded device memory: every candidate length searched as in
+ * pst_snippets_blocked (blocks of min(seg_block, n/m) segments), one length
+ * after another, its criterion computed from the K kept profiles; then the
+ * chosen length once more for out_host / profiles_dev / owner_dev.  Scores,
+ * m_best and the outputs are bit-identical to pst_select_length's.  The
+ * workspace must hold pst_select_length_blocked_workspace_bytes(...) bytes (0
+ * for invalid sizes): the largest single candidate's, not the sum.  Errors as
+ * pst_select_length, plus PST_EINVAL for seg_block < 1. */
+size_t pst_select_length_blocked_workspace_bytes(int64_t n, const int32_t *m_list, int32_t num_m,
+                                                 const int32_t *l_list, int32_t K, int32_t seg_block);
+int pst_select_length_blocked(pst_ctx *ctx, const double *T_dev, int64_t n,
+                              const int32_t *m_list, int32_t num_m, const int32_t *l_list,
+                              int32_t K, int32_t seg_block, int32_t *m_best, double *scores_host,
+                              pst_snippet *out_host, float *profiles_dev, int32_t *owner_dev,
+                              void *ws_dev, size_t ws_bytes);
+
 /* Multivariate series (eqs. 1-2): d coordinates of length n, coordinate j
  * at T_dev + j*ld (float64, ld >= n).  Section 3.2 runs the snippet search on
  * each coordinate independently; here every coordinate's profile set runs in

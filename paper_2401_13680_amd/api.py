@@ -221,6 +221,38 @@ def select_length(T, m_list, K: int, l_list=None, profiles: bool = False, owner:
     return dict(m_best=mb, scores=list(scores), records=_records(recs, K), profiles=prof, owner=own)
 
 
+def select_length_blocked(T, m_list, K: int, seg_block: int, l_list=None, profiles: bool = False,
+                          owner: bool = False, ctx: Context | None = None):
+    """eq. 18 in bounded memory: select_length's result, every candidate's
+    profile set recomputed per greedy round in blocks of seg_block segments."""
+    T = _series(T)
+    ctx = ctx or context(T.device.index)
+    n = T.numel()
+    num = len(m_list)
+    ms = (c_int32 * num)(*m_list)
+    ls = (c_int32 * num)(*l_list) if l_list is not None else None
+    nb = ctx.L.pst_select_length_blocked_workspace_bytes(n, ms, num, ls, K, seg_block)
+    if nb == 0:
+        raise PstError(-1, "invalid sizes in the candidate list")
+    scores = (c_double * num)()
+    best = c_int32()
+    recs = (Snippet * K)()
+    ws = ctx.workspace(nb)
+    Nm_max = n - min(m_list) + 1
+    prof = torch.empty((K, Nm_max), dtype=torch.float32, device=T.device) if profiles else None
+    own = torch.empty(Nm_max, dtype=torch.int32, device=T.device) if owner else None
+    ctx.check(ctx.L.pst_select_length_blocked(ctx.h, _ptr(T), n, ms, num, ls, K, seg_block, byref(best), scores,
+                                               recs, _ptr(prof), _ptr(own), _ptr(ws), ws.numel()))
+    mb = int(best.value)
+    Nm = n - mb + 1
+    if prof is not None:
+        prof = prof.view(-1)[: K * Nm].view(K, Nm)
+    if own is not None:
+        own = own[:Nm]
+    return dict(m_best=mb, scores=list(scores), records=_records(recs, K), profiles=prof, owner=own,
+                workspace_bytes=nb)
+
+
 def label_f1(owner, truth, m: int, K: int, C: int, ctx: Context | None = None):
     """Labelling score of K snippets (section 5.2's per-element F1): owner is
     the int32 owner array of snippets() (n-m+1 windows), truth the int32 true

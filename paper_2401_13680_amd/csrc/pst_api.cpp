@@ -342,7 +342,7 @@ int run_multi(pst_ctx *c, const MultiPlan &P, const double *T, int64_t ldT, char
 struct BlockedLayout {
     Layout L;            // sizes (its D and scratch regions are not used)
     int32_t B = 0, grid = 0;
-    size_t o_T, o_Dblk, o_P, o_M, o_part, o_pick, o_area, o_chosen, o_count, o_iota, o_dmax, o_rw, total;
+    size_t o_T, o_Dblk, o_P, o_M, o_part, o_pick, o_area, o_chosen, o_count, o_iota, o_dmax, o_crit, o_rw, total;
 };
 
 int plan_blocked(pst_ctx *c, int64_t n, int32_t m, int32_t l, int32_t k, int32_t K, int32_t B, BlockedLayout *P) {
@@ -365,6 +365,7 @@ int plan_blocked(pst_ctx *c, int64_t n, int32_t m, int32_t l, int32_t k, int32_t
     P->o_count = o;  o = al(o + sizeof(int32_t) * K);
     P->o_iota = o;   o = al(o + sizeof(int32_t) * K);
     P->o_dmax = o;   o = al(o + 256);
+    P->o_crit = o;   o = al(o + sizeof(double) * (L.nblk2 + 1));
     P->o_rw = o;     o = al(o + sizeof(float) * profile_scratch_floats(P->grid, L.w));
     P->total = o;
     return PST_OK;
@@ -383,7 +384,7 @@ Stats rows_from(Stats s, int64_t off) {
 }
 
 int run_blocked(pst_ctx *c, const BlockedLayout &P, const double *T, char *ws, pst_snippet *out, float *profiles,
-                int32_t *owner, float *dmax_host) {
+                int32_t *owner, float *dmax_host, double *score_host = nullptr) {
     const Layout &L = P.L;
     int rc = series_stats(c, T, ws + P.o_T, L.sT, "T");
     if (rc) return rc;
@@ -457,12 +458,18 @@ int run_blocked(pst_ctx *c, const BlockedLayout &P, const double *T, char *ws, p
     Go.owner = owner;
     Go.profiles = profiles;
     HIPCHK(c, launch_owner(Go, c->stream));
-    Layout Lr = L;  // collect_records reads picks, areas, counts and max at these offsets
+    if (score_host) {  // eq. 18's numerator over the kept rows
+        Go.crit = (double *)(ws + P.o_crit);
+        Go.nblk2 = L.nblk2;
+        HIPCHK(c, launch_criterion(Go, c->stream));
+    }
+    Layout Lr = L;  // collect_records reads picks, areas, counts, max and criterion at these offsets
     Lr.o_pick = P.o_pick;
     Lr.o_area = P.o_area;
     Lr.o_count = P.o_count;
     Lr.o_dmax = P.o_dmax;
-    return collect_records(c, Lr, ws, out, dmax_host, nullptr);
+    Lr.o_crit = P.o_crit;
+    return collect_records(c, Lr, ws, out, dmax_host, score_host);
 }
 
 // ---------------------------------------------------------------- length sweep
@@ -1000,6 +1007,59 @@ int pst_snippets_blocked(pst_ctx *ctx, const double *T_dev, int64_t n, int32_t m
     if (((uintptr_t)ws_dev & 255) != 0) return fail(ctx, PST_EINVAL, "workspace must be 256-byte aligned");
     if (ws_bytes < P.total) return fail(ctx, PST_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, P.total);
     return run_blocked(ctx, P, T_dev, (char *)ws_dev, out_host, profiles_dev, owner_dev, dmax_host);
+}
+
+size_t pst_select_length_blocked_workspace_bytes(int64_t n, const int32_t *m_list, int32_t num_m,
+                                                 const int32_t *l_list, int32_t K, int32_t seg_block) {
+    if (!m_list || num_m < 1 || num_m > kMaxJobs || seg_block < 1) return 0;
+    size_t mx = 0;
+    for (int i = 0; i < num_m; ++i) {
+        const int32_t l = l_list ? l_list[i] : m_list[i] / 2;
+        if (m_list[i] < 1) return 0;
+        const int64_t nseg = n / m_list[i];
+        const size_t b = pst_snippets_blocked_workspace_bytes(n, m_list[i], l, K, (int32_t)std::min<int64_t>(seg_block, nseg));
+        if (b == 0) return 0;
+        mx = std::max(mx, b);
+    }
+    return mx;
+}
+
+int pst_select_length_blocked(pst_ctx *ctx, const double *T_dev, int64_t n, const int32_t *m_list, int32_t num_m,
+                              const int32_t *l_list, int32_t K, int32_t seg_block, int32_t *m_best,
+                              double *scores_host, pst_snippet *out_host, float *profiles_dev, int32_t *owner_dev,
+                              void *ws_dev, size_t ws_bytes) {
+    int rc = begin(ctx);
+    if (rc) return rc;
+    if (!m_list || num_m < 1 || !m_best || !T_dev)
+        return fail(ctx, PST_EINVAL, "need a candidate list, m_best and T");
+    if (num_m > kMaxJobs) return fail(ctx, PST_EINVAL, "at most %d candidate lengths", kMaxJobs);
+    if (seg_block < 1) return fail(ctx, PST_EINVAL, "need seg_block >= 1 (seg_block=%d)", seg_block);
+    if (!ws_dev) return fail(ctx, PST_EINVAL, "workspace is NULL");
+    if (((uintptr_t)ws_dev & 255) != 0) return fail(ctx, PST_EINVAL, "workspace must be 256-byte aligned");
+    std::vector<BlockedLayout> P(num_m);
+    for (int i = 0; i < num_m; ++i) {
+        const int32_t l = l_list ? l_list[i] : m_list[i] / 2;
+        if (m_list[i] < 2) return fail(ctx, PST_EINVAL, "need m >= 2 (m=%d)", m_list[i]);
+        const int32_t B = (int32_t)std::min<int64_t>(seg_block, n / m_list[i]);
+        if ((rc = plan_blocked(ctx, n, m_list[i], l, 0, K, std::max(B, 1), &P[i]))) return rc;
+        if (ws_bytes < P[i].total)
+            return fail(ctx, PST_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, P[i].total);
+    }
+    char *ws = (char *)ws_dev;
+    int best = -1;
+    double best_score = 0.0;
+    for (int i = 0; i < num_m; ++i) {
+        double score = 0.0;
+        if ((rc = run_blocked(ctx, P[i], T_dev, ws, nullptr, nullptr, nullptr, nullptr, &score))) return rc;
+        if (scores_host) scores_host[i] = score;
+        if (best < 0 || score > best_score || (score == best_score && m_list[i] < m_list[best])) {
+            best = i;
+            best_score = score;
+        }
+    }
+    *m_best = m_list[best];
+    // the chosen length once more, now keeping its snippets, owners and profiles
+    return run_blocked(ctx, P[best], T_dev, ws, out_host, profiles_dev, owner_dev, nullptr);
 }
 
 size_t pst_snippets_multi_workspace_bytes(int32_t d, int64_t n, int32_t m, int32_t l, int32_t K) {

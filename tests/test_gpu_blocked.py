@@ -75,3 +75,21 @@ def test_blocked_sizes_and_errors():
         api.snippets_blocked(bad, 100, 50, 3, seg_block=4)
     r = api.snippets_blocked(T, 100, 50, 3, seg_block=4)
     assert len(r["records"]) == 3
+
+
+def test_blocked_sweep_equals_in_core_sweep():
+    x = synth.regime_series(20_000, 12, synth.SHAPES6, len_range=(1000, 3000)).x
+    T = torch.from_numpy(x).cuda()
+    ms, K = [40, 64, 96, 128], 3
+    print("blocked sweep: n=20000 m in {40, 64, 96, 128} seg_block=37", flush=True)
+    ref = api.select_length(T, ms, K, profiles=True, owner=True)
+    got = api.select_length_blocked(T, ms, K, seg_block=37, profiles=True, owner=True)
+    assert got["m_best"] == ref["m_best"]
+    assert got["scores"] == ref["scores"]
+    assert got["records"] == ref["records"]
+    assert torch.equal(got["owner"], ref["owner"]) and torch.equal(got["profiles"], ref["profiles"])
+    # the workspace is the largest candidate's, far below the batched sweep's
+    L = api.context(0).L
+    import ctypes
+    arr = (ctypes.c_int32 * 4)(*ms)
+    assert got["workspace_bytes"] < L.pst_select_length_workspace_bytes(20_000, arr, 4, None, K)
