@@ -223,7 +223,8 @@ def schedule_bench(args):
 
 def blocked_bench(args):
     """Bounded memory: a 10^6-point five-shape series, m=256, l=128, K=4 (profile
-    set 15.6 GB), in core against pst_snippets_blocked with a 4 GiB workspace."""
+    set 15.6 GB), in core against pst_snippets_blocked with a 4 GiB workspace, and
+    against pst_snippets_spilled (the same workspace, D kept in pinned host memory)."""
     import torch
 
     from paper_2401_13680_amd import api, synth
@@ -232,11 +233,14 @@ def blocked_bench(args):
     T = torch.from_numpy(synth.regime_series(n, 8, synth.SHAPES5).x).cuda()
     cells = (n // m) * (m - l + 1) * (n - l + 1)
     res = {}
-    for mode in ("in_core", "blocked"):
+    D_host = torch.empty((n // m, n - m + 1), dtype=torch.float32, pin_memory=True)
+    for mode in ("in_core", "blocked", "spilled"):
         def step():
             if mode == "in_core":
                 return api.snippets(T, m, l, K, owner=True)
-            return api.snippets_blocked(T, m, l, K, budget_bytes=4 << 30, owner=True)
+            if mode == "blocked":
+                return api.snippets_blocked(T, m, l, K, budget_bytes=4 << 30, owner=True)
+            return api.snippets_spilled(T, m, l, K, budget_bytes=4 << 30, D_host=D_host, owner=True)
         step()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -253,6 +257,9 @@ def blocked_bench(args):
                blocked=dict(seconds=round(res["blocked"][0], 4), workspace_bytes=rb["workspace_bytes"],
                             seg_block=rb["seg_block"], segments=n // m,
                             cells_per_s_of_the_problem=cells / res["blocked"][0]),
+               spilled=dict(seconds=round(res["spilled"][0], 4), workspace_bytes=res["spilled"][1]["workspace_bytes"],
+                            host_bytes=D_host.numel() * 4, cells_per_s_of_the_problem=cells / res["spilled"][0],
+                            identical=res["spilled"][1]["records"] == res["in_core"][1]["records"]),
                time_ratio=res["blocked"][0] / res["in_core"][0],
                memory_ratio=ws_in / rb["workspace_bytes"],
                identical=(rb["records"] == res["in_core"][1]["records"]

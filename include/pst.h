@@ -139,6 +139,17 @@ int pst_snippets_blocked(pst_ctx *ctx, const double *T_dev, int64_t n, int32_t m
                          float *profiles_dev, int32_t *owner_dev, float *dmax_host,
                          void *ws_dev, size_t ws_bytes);
 
+/* As pst_snippets_blocked, with the profile set spilled to host memory
+ * instead of recomputed: it is computed once, block by block, and copied to
+ * D_host (float32[n/m][n-m+1], row s = D_s, caller-owned; page-locked memory
+ * from hipHostMalloc, or the copies are slow); later greedy rounds and the
+ * picked rows are copied back from it.  Same workspace, same bit-identical
+ * results; D_host holds the whole profile set on return. */
+int pst_snippets_spilled(pst_ctx *ctx, const double *T_dev, int64_t n, int32_t m, int32_t l,
+                         int32_t k, int32_t K, int32_t seg_block, float *D_host,
+                         pst_snippet *out_host, float *profiles_dev, int32_t *owner_dev,
+                         float *dmax_host, void *ws_dev, size_t ws_bytes);
+
 /* eq. 18 in bounded device memory: every candidate length searched as in
  * pst_snippets_blocked (blocks of min(seg_block, n/m) segments), one length
  * after another, its criterion computed from the K kept profiles; then the

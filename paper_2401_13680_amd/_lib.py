@@ -71,6 +71,8 @@ def load():
         "pst_snippets_blocked_max_block": (c_int32, [c_int64, c_int32, c_int32, c_int32, c_size_t]),
         "pst_snippets_blocked": (c_int, [P, P, c_int64, c_int32, c_int32, c_int32, c_int32, c_int32,
                                          POINTER(Snippet), P, P, POINTER(c_float), P, c_size_t]),
+        "pst_snippets_spilled": (c_int, [P, P, c_int64, c_int32, c_int32, c_int32, c_int32, c_int32, P,
+                                         POINTER(Snippet), P, P, POINTER(c_float), P, c_size_t]),
         "pst_select_length_blocked_workspace_bytes": (c_size_t, [c_int64, POINTER(c_int32), c_int32,
                                                                  POINTER(c_int32), c_int32, c_int32]),
         "pst_select_length_blocked": (c_int, [P, P, c_int64, POINTER(c_int32), c_int32, POINTER(c_int32), c_int32,

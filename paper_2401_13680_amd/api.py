@@ -221,6 +221,38 @@ def select_length(T, m_list, K: int, l_list=None, profiles: bool = False, owner:
     return dict(m_best=mb, scores=list(scores), records=_records(recs, K), profiles=prof, owner=own)
 
 
+def snippets_spilled(T, m: int, l: int, K: int, seg_block: int = 0, k: int = 0, budget_bytes: int = 0,
+                     D_host=None, profiles: bool = False, owner: bool = False, ctx: Context | None = None):
+    """snippets_blocked with the profile set kept in page-locked host memory
+    (D_host, float32 (n/m, n-m+1), allocated when None) instead of recomputed
+    every greedy round."""
+    T = _series(T)
+    ctx = ctx or context(T.device.index)
+    n = T.numel()
+    if seg_block <= 0:
+        seg_block = int(ctx.L.pst_snippets_blocked_max_block(n, m, l, K, budget_bytes))
+        if seg_block <= 0:
+            raise PstError(-1, f"no block fits {budget_bytes} bytes (n={n} m={m} l={l} K={K})")
+    nb = ctx.L.pst_snippets_blocked_workspace_bytes(n, m, l, K, seg_block)
+    if nb == 0:
+        raise PstError(-1, f"invalid sizes n={n} m={m} l={l} K={K} seg_block={seg_block}")
+    Nm = n - m + 1
+    if D_host is None:
+        D_host = torch.empty((n // m, Nm), dtype=torch.float32, pin_memory=True)
+    if not (D_host.dtype == torch.float32 and not D_host.is_cuda and D_host.is_contiguous()
+            and tuple(D_host.shape) == (n // m, Nm)):
+        raise ValueError("D_host must be a contiguous float32 host tensor of shape (n/m, n-m+1)")
+    prof = torch.empty((K, Nm), dtype=torch.float32, device=T.device) if profiles else None
+    own = torch.empty(Nm, dtype=torch.int32, device=T.device) if owner else None
+    recs = (Snippet * K)()
+    dmax = c_float()
+    ws = ctx.workspace(nb)
+    ctx.check(ctx.L.pst_snippets_spilled(ctx.h, _ptr(T), n, m, l, k, K, seg_block, _ptr(D_host), recs, _ptr(prof),
+                                          _ptr(own), byref(dmax), _ptr(ws), ws.numel()))
+    return dict(records=_records(recs, K), profiles=prof, owner=own, dmax=float(dmax.value),
+                seg_block=seg_block, workspace_bytes=nb, D_host=D_host)
+
+
 def select_length_blocked(T, m_list, K: int, seg_block: int, l_list=None, profiles: bool = False,
                           owner: bool = False, ctx: Context | None = None):
     """eq. 18 in bounded memory: select_length's result, every candidate's

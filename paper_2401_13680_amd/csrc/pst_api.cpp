@@ -383,8 +383,12 @@ Stats rows_from(Stats s, int64_t off) {
     return s;
 }
 
+// With D_host (pinned, nseg x Nm floats) the profile set is computed once:
+// round 0 copies every block out after its area partials, later rounds copy
+// the blocks back instead of recomputing them, and the picked rows come from
+// host memory too.  Without it every round recomputes the blocks.
 int run_blocked(pst_ctx *c, const BlockedLayout &P, const double *T, char *ws, pst_snippet *out, float *profiles,
-                int32_t *owner, float *dmax_host, double *score_host = nullptr) {
+                int32_t *owner, float *dmax_host, double *score_host = nullptr, float *D_host = nullptr) {
     const Layout &L = P.L;
     int rc = series_stats(c, T, ws + P.o_T, L.sT, "T");
     if (rc) return rc;
@@ -420,13 +424,22 @@ int run_blocked(pst_ctx *c, const BlockedLayout &P, const double *T, char *ws, p
     for (int r = 0; r < L.K; ++r) {
         for (int32_t s0 = 0; s0 < L.nseg; s0 += P.B) {
             const int32_t nb = std::min(P.B, L.nseg - s0);
-            ProfileJob j = base;
-            j.row = rows_from(st, (int64_t)s0 * L.m);
-            j.nq = nb;
-            j.D = Dblk;
-            j.dmax_bits = r == 0 ? dmax : nullptr;
-            j.grid = profile_grid(L.ntile * (int64_t)nb, L.w);
-            HIPCHK(c, launch_profile_batch(&j, 1, j.grid, nullptr, c->stream));
+            float *hblk = D_host ? D_host + (size_t)s0 * L.Nm : nullptr;
+            if (r == 0 || !D_host) {
+                ProfileJob j = base;
+                j.row = rows_from(st, (int64_t)s0 * L.m);
+                j.nq = nb;
+                j.D = Dblk;
+                j.dmax_bits = r == 0 ? dmax : nullptr;
+                j.grid = profile_grid(L.ntile * (int64_t)nb, L.w);
+                HIPCHK(c, launch_profile_batch(&j, 1, j.grid, nullptr, c->stream));
+                if (D_host)
+                    HIPCHK(c, hipMemcpyAsync(hblk, Dblk, sizeof(float) * (size_t)nb * L.Nm, hipMemcpyDeviceToHost,
+                                             c->stream));
+            } else {
+                HIPCHK(c, hipMemcpyAsync(Dblk, hblk, sizeof(float) * (size_t)nb * L.Nm, hipMemcpyHostToDevice,
+                                         c->stream));
+            }
             GreedyJob Gb = G;
             Gb.D = Dblk;
             Gb.nseg = nb;
@@ -438,14 +451,20 @@ int run_blocked(pst_ctx *c, const BlockedLayout &P, const double *T, char *ws, p
         int32_t pk = 0;
         HIPCHK(c, hipMemcpyAsync(&pk, G.pick + r, sizeof pk, hipMemcpyDeviceToHost, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
-        // the picked segment's profile, alone, kept as row r
-        ProfileJob j = base;
-        j.row = rows_from(st, (int64_t)pk * L.m);
-        j.nq = 1;
-        j.D = Prow + (size_t)r * L.Nm;
-        j.dmax_bits = nullptr;
-        j.grid = profile_grid(L.ntile, L.w);
-        HIPCHK(c, launch_profile_batch(&j, 1, j.grid, nullptr, c->stream));
+        // the picked segment's profile, kept as row r: recomputed alone, or
+        // copied back from host memory
+        if (D_host) {
+            HIPCHK(c, hipMemcpyAsync(Prow + (size_t)r * L.Nm, D_host + (size_t)pk * L.Nm, sizeof(float) * L.Nm,
+                                     hipMemcpyHostToDevice, c->stream));
+        } else {
+            ProfileJob j = base;
+            j.row = rows_from(st, (int64_t)pk * L.m);
+            j.nq = 1;
+            j.D = Prow + (size_t)r * L.Nm;
+            j.dmax_bits = nullptr;
+            j.grid = profile_grid(L.ntile, L.w);
+            HIPCHK(c, launch_profile_batch(&j, 1, j.grid, nullptr, c->stream));
+        }
         GreedyJob Gk = G;
         Gk.D = Prow;
         Gk.pick = (int32_t *)(ws + P.o_iota);
@@ -1007,6 +1026,20 @@ int pst_snippets_blocked(pst_ctx *ctx, const double *T_dev, int64_t n, int32_t m
     if (((uintptr_t)ws_dev & 255) != 0) return fail(ctx, PST_EINVAL, "workspace must be 256-byte aligned");
     if (ws_bytes < P.total) return fail(ctx, PST_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, P.total);
     return run_blocked(ctx, P, T_dev, (char *)ws_dev, out_host, profiles_dev, owner_dev, dmax_host);
+}
+
+int pst_snippets_spilled(pst_ctx *ctx, const double *T_dev, int64_t n, int32_t m, int32_t l, int32_t k, int32_t K,
+                         int32_t seg_block, float *D_host, pst_snippet *out_host, float *profiles_dev,
+                         int32_t *owner_dev, float *dmax_host, void *ws_dev, size_t ws_bytes) {
+    int rc = begin(ctx);
+    if (rc) return rc;
+    BlockedLayout P;
+    if ((rc = plan_blocked(ctx, n, m, l, k, K, seg_block, &P))) return rc;
+    if (!T_dev || !out_host || !D_host) return fail(ctx, PST_EINVAL, "null pointer argument");
+    if (!ws_dev) return fail(ctx, PST_EINVAL, "workspace is NULL");
+    if (((uintptr_t)ws_dev & 255) != 0) return fail(ctx, PST_EINVAL, "workspace must be 256-byte aligned");
+    if (ws_bytes < P.total) return fail(ctx, PST_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, P.total);
+    return run_blocked(ctx, P, T_dev, (char *)ws_dev, out_host, profiles_dev, owner_dev, dmax_host, nullptr, D_host);
 }
 
 size_t pst_select_length_blocked_workspace_bytes(int64_t n, const int32_t *m_list, int32_t num_m,

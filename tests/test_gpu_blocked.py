@@ -93,3 +93,16 @@ def test_blocked_sweep_equals_in_core_sweep():
     import ctypes
     arr = (ctypes.c_int32 * 4)(*ms)
     assert got["workspace_bytes"] < L.pst_select_length_workspace_bytes(20_000, arr, 4, None, K)
+
+
+def test_spilled_equals_in_core():
+    x = synth.workload_series("regimes5_n100000")
+    m, l, K = 256, 128, 4
+    T = torch.from_numpy(x).cuda()
+    ref = api.snippets(T, m, l, K, profiles=True, owner=True)
+    D, _ = api.profile_set(T, m, l)
+    for B in (1, 64, 390):
+        print(f"spilled: regimes5_n100000 seg_block={B}", flush=True)
+        got = api.snippets_spilled(T, m, l, K, seg_block=B, profiles=True, owner=True)
+        _same(got, ref)
+        assert torch.equal(got["D_host"], D.cpu())   # the whole profile set, as computed in core
