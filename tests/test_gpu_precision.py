@@ -2,9 +2,11 @@
 (m=512, l=256, k=52): profile error of the FP32 recurrence against the FP64
 oracle, for the default anchoring (an FP64 anchor at the first cell of every
 diagonal of a sub-tile, so at most w-1 = 256 FP32 steps) and for extra FP64
-re-anchors every R rows.  Re-anchor intervals R >= 256 coincide with the
-default here.  Errors are measured on sampled profile entries, each computed
-by the oracle on its own."""
+re-anchors every R rows, R in {128, 32} and the study's {256, 1024, 4096}.
+With w = 257 rows per sub-tile, R = 256 adds one re-anchor (row 256) and
+R >= 1024 none: those profiles are bit-identical to the default's.  Errors
+are measured on sampled profile entries, each computed by the oracle on its
+own."""
 import math
 import time
 
@@ -31,19 +33,27 @@ def test_precision_walk_n1000000():
     ref = oracle.mpdist_pairs_local(x, m, l, k, pairs)
     ctx = api.context(0)
     rows = []
-    for R in (0, 128, 32):
+    D0 = None
+    for R in (0, 4096, 1024, 256, 128, 32):
         ctx.check(ctx.L.pst_set_option(ctx.h, _lib.PST_OPT_ANCHOR_EVERY, R))
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         D, _ = api.profile_set(T, m, l, k, ctx=ctx)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        got = D.cpu().numpy()[tuple(np.array(pairs).T)].astype(np.float64)
-        del D
+        if R == 0:
+            D0 = D
+        elif R >= 1024:
+            assert torch.equal(D, D0), R          # no re-anchor inside a sub-tile
+        idx = torch.from_numpy(np.array(pairs).T.copy()).cuda()
+        got = D[idx[0], idx[1]].cpu().numpy().astype(np.float64)
+        if R != 0:
+            del D
         e = np.abs(got ** 2 - ref ** 2) / (4 * l)
         mask = ref >= 0.1 * math.sqrt(l)
         rel = np.abs(got - ref)[mask] / ref[mask]
         rows.append((R, dt, e.max(), e.mean(), rel.max(), rel.mean()))
+    del D0
     ctx.check(ctx.L.pst_set_option(ctx.h, _lib.PST_OPT_ANCHOR_EVERY, 0))
     print("\nR(0=per sub-tile)  seconds  max_e  mean_e  max_rel  mean_rel")
     for r in rows:
