@@ -228,7 +228,8 @@ int  pst_model_predict(const pst_model *model, int64_t n, int32_t m, int32_t l, 
  * of the first with smallest of the second, and the merged slots re-sorted
  * largest first (stable), until one tuple is left.  part_out[i]: the part of
  * item i (parts numbered by load, largest first); load_out[parts]: each part's
- * summed cost.  PST_EINVAL for a negative or non-finite cost. */
+ * summed cost.  PST_EINVAL for a negative or non-finite cost, or when
+ * count * parts exceeds 2^24 (the merge tuples hold count * parts sums). */
 int  pst_partition_kk(const double *cost, int32_t count, int32_t parts, int32_t *part_out,
                       double *load_out);
 /* The candidate lengths of eq. 18 (l_list NULL: l = m/2) spread over `parts`

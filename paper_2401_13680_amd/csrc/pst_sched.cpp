@@ -228,6 +228,7 @@ int pst_model_predict(const pst_model *M, int64_t n, int32_t m, int32_t l, doubl
 int pst_partition_kk(const double *cost, int32_t count, int32_t parts, int32_t *part_out, double *load_out) {
     if (count < 0 || parts < 1 || parts > 4096 || (count > 0 && (!cost || !part_out)) || !load_out)
         return PST_EINVAL;
+    if ((int64_t)count * parts > ((int64_t)1 << 24)) return PST_EINVAL;  // the tuples take count * parts slots
     for (int i = 0; i < count; ++i)
         if (!(cost[i] >= 0.0) || !std::isfinite(cost[i])) return PST_EINVAL;
     std::vector<int> po(count);

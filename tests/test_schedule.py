@@ -172,3 +172,5 @@ def test_library_errors():
         api.partition_kk([1.0, float("nan")], 2)
     with pytest.raises(PstError):
         api.partition_kk([1.0], 0)
+    with pytest.raises(PstError):
+        api.partition_kk([1.0] * 5000, 4096)   # 5000 x 4096 slots > 2^24
