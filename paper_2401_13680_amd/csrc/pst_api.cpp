@@ -499,6 +499,7 @@ int run_blocked(pst_ctx *c, const BlockedLayout &P, const double *T, char *ws, p
 struct SweepPlan {
     int nm = 0, K = 0;
     int32_t wmax = 0, grid = 0;
+    int32_t wsmall = 0, grid_small = 0;  // jobs of the other workgroup shape (0: none)
     std::vector<Layout> L;        // per candidate: sizes
     std::vector<int32_t> ls;      // distinct l
     std::vector<StatsLayout> SL;  // statistics layout per distinct l
@@ -540,8 +541,14 @@ int plan_sweep(pst_ctx *c, int64_t n, const int32_t *m_list, int32_t nm, const i
         o = al(o + P->SL.back().total);
     }
     P->grid = profile_slots(P->wmax);
+    // lengths whose own workgroup shape differs from the widest one's run in a
+    // second launch of that shape
+    for (int i = 0; i < nm; ++i)
+        if (profile_slots(P->L[i].w) != P->grid) P->wsmall = std::max(P->wsmall, P->L[i].w);
+    P->grid_small = P->wsmall ? profile_slots(P->wsmall) : 0;
     P->o_rw = o;
-    o = al(o + sizeof(float) * profile_scratch_floats(P->grid, P->wmax));
+    o = al(o + sizeof(float) * std::max(profile_scratch_floats(P->grid, P->wmax),
+                                        P->wsmall ? profile_scratch_floats(P->grid_small, P->wsmall) : (size_t)0));
     P->o_counter = o;
     o = al(o + 256);
     for (int i = 0; i < nm; ++i) {
@@ -616,6 +623,30 @@ int sweep_jobs(const SweepPlan &P, char *ws, int32_t grid, ProfileJob *jobs, int
     return P.nm;
 }
 
+// The profile launches of a sweep: one persistent launch with every length,
+// or, when some lengths have a different workgroup shape from the widest, one
+// launch per shape (the grid of the second scaled like the first's).
+hipError_t launch_sweep_profiles(const SweepPlan &P, char *ws, int32_t grid, bool dynamic, hipStream_t st,
+                                 int32_t anchor) {
+    ProfileJob jobs[kMaxJobs];
+    const int nj = sweep_jobs(P, ws, grid, jobs, anchor);
+    uint32_t *counter = (uint32_t *)(ws + P.o_counter);
+    hipError_t e;
+    if (!P.wsmall) {
+        if ((e = launch_fill_u32(counter, 1, 0u, st)) != hipSuccess) return e;
+        return launch_profile_batch(jobs, nj, grid, dynamic ? counter : nullptr, st);
+    }
+    std::stable_partition(jobs, jobs + nj, [&](const ProfileJob &j) { return profile_slots(j.w) == P.grid; });
+    int nb = 0;
+    while (nb < nj && profile_slots(jobs[nb].w) == P.grid) ++nb;
+    const int32_t gs = std::max<int32_t>(1, (int32_t)((int64_t)P.grid_small * grid / P.grid));
+    for (int j = nb; j < nj; ++j) jobs[j].grid = gs;
+    if ((e = launch_fill_u32(counter, 1, 0u, st)) != hipSuccess) return e;
+    if ((e = launch_profile_batch(jobs, nb, grid, dynamic ? counter : nullptr, st)) != hipSuccess) return e;
+    if ((e = launch_fill_u32(counter, 1, 0u, st)) != hipSuccess) return e;
+    return launch_profile_batch(jobs + nb, nj - nb, gs, dynamic ? counter : nullptr, st);
+}
+
 hipError_t enqueue_sweep(const SweepPlan &P, const double *T, char *ws, int32_t grid, bool dynamic,
                          hipStream_t st, int32_t anchor) {
     hipError_t e;
@@ -623,11 +654,7 @@ hipError_t enqueue_sweep(const SweepPlan &P, const double *T, char *ws, int32_t 
         if ((e = launch_series_stats(T, ws + P.o_stats[j], P.SL[j], st)) != hipSuccess) return e;
     for (int i = 0; i < P.nm; ++i)
         if ((e = launch_fill_u32((uint32_t *)(ws + P.gb[i].dmax), 1, 0u, st)) != hipSuccess) return e;
-    uint32_t *counter = (uint32_t *)(ws + P.o_counter);
-    if ((e = launch_fill_u32(counter, 1, 0u, st)) != hipSuccess) return e;
-    ProfileJob jobs[kMaxJobs];
-    const int nj = sweep_jobs(P, ws, grid, jobs, anchor);
-    if ((e = launch_profile_batch(jobs, nj, grid, dynamic ? counter : nullptr, st)) != hipSuccess) return e;
+    if ((e = launch_sweep_profiles(P, ws, grid, dynamic, st, anchor)) != hipSuccess) return e;
     SweepGather Gt{};
     Gt.nm = P.nm;
     Gt.K = P.K;
@@ -709,13 +736,11 @@ int autotune(pst_ctx *c, const SweepPlan &P, const double *T, char *ws, TuneVal 
     HIPCHK(c, hipEventCreate(&a));
     HIPCHK(c, hipEventCreate(&b));
     TuneVal best{S, 1, 1e30f};
+    HIPCHK(c, profile_prepare(P.wmax));
+    if (P.wsmall) HIPCHK(c, profile_prepare(P.wsmall));
     for (const auto &cf : cand) {
-        ProfileJob jobs[kMaxJobs];
-        const int nj = sweep_jobs(P, ws, cf[0], jobs);
-        uint32_t *counter = (uint32_t *)(ws + P.o_counter);
-        HIPCHK(c, launch_fill_u32(counter, 1, 0u, c->stream));
         HIPCHK(c, hipEventRecord(a, c->stream));
-        HIPCHK(c, launch_profile_batch(jobs, nj, cf[0], cf[1] ? counter : nullptr, c->stream));
+        HIPCHK(c, launch_sweep_profiles(P, ws, cf[0], cf[1] != 0, c->stream, 0));
         HIPCHK(c, hipEventRecord(b, c->stream));
         HIPCHK(c, hipEventSynchronize(b));
         float ms = 0.0f;
@@ -745,6 +770,7 @@ int run_sweep(pst_ctx *c, const SweepPlan &P, const double *T, char *ws, size_t 
         if (rc) return rc;
     }
     HIPCHK(c, profile_prepare(P.wmax));
+    if (P.wsmall) HIPCHK(c, profile_prepare(P.wsmall));
     if (!c->opt_graph) {
         HIPCHK(c, enqueue_sweep(P, T, ws, cfg.grid, cfg.dynamic != 0, c->stream, c->opt_anchor));
     } else {

@@ -226,6 +226,25 @@ def test_sweep_batched_graph_equals_plain_and_oracle():
     assert_profiles_close(g["profiles"].cpu().numpy(), Dref[picks], g["m_best"] // 2, "sweep profiles")
 
 
+def test_sweep_across_workgroup_shapes():
+    """Lengths whose profile kernels use different workgroup shapes (w = 25
+    and 33 with 256 threads, w = 191 and 257 with 512) run as two launches in
+    the batched sweep: same scores and snippets as one length at a time, and
+    the oracle's choice."""
+    x = synth.regime_series(4000, 15, len_range=(600, 1500)).x
+    ms = [48, 64, 380, 512]
+    T = dev(x)
+    print("sweep: n=4000 m in {48, 64, 380, 512}", flush=True)
+    plain = api.select_length(T, ms, 2, batched=False)
+    for graph in (False, True):
+        b = api.select_length(T, ms, 2, batched=True, graph=graph)
+        assert _sweep_key(b) == _sweep_key(plain), graph
+    ref = oracle.select_length(x, ms, 2)
+    for a, r in zip(plain["scores"], ref["scores"]):
+        assert abs(a - r) <= 1e-3 * max(1.0, abs(r))
+    assert plain["m_best"] == ref["m_best"]
+
+
 def test_sweep_autotune_same_result(tmp_path, monkeypatch):
     monkeypatch.setenv("PST_AUTOTUNE_CACHE", str(tmp_path / "tune.txt"))
     x = synth.regime_series(5000, 14, len_range=(500, 1500)).x
