@@ -8,6 +8,7 @@
 #include <cmath>
 #include <condition_variable>
 #include <deque>
+#include <functional>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
@@ -499,7 +500,7 @@ int run_blocked(pst_ctx *c, const BlockedLayout &P, const double *T, char *ws, p
 struct SweepPlan {
     int nm = 0, K = 0;
     int32_t wmax = 0, grid = 0;
-    int32_t wsmall = 0, grid_small = 0;  // jobs of the other workgroup shape (0: none)
+    std::vector<int32_t> shape_w;  // widest w of each workgroup shape among the lengths, widest first
     std::vector<Layout> L;        // per candidate: sizes
     std::vector<int32_t> ls;      // distinct l
     std::vector<StatsLayout> SL;  // statistics layout per distinct l
@@ -541,14 +542,21 @@ int plan_sweep(pst_ctx *c, int64_t n, const int32_t *m_list, int32_t nm, const i
         o = al(o + P->SL.back().total);
     }
     P->grid = profile_slots(P->wmax);
-    // lengths whose own workgroup shape differs from the widest one's run in a
-    // second launch of that shape
-    for (int i = 0; i < nm; ++i)
-        if (profile_slots(P->L[i].w) != P->grid) P->wsmall = std::max(P->wsmall, P->L[i].w);
-    P->grid_small = P->wsmall ? profile_slots(P->wsmall) : 0;
+    // lengths of each workgroup shape run in a launch of that shape
+    std::vector<int32_t> ws_sorted;
+    for (int i = 0; i < nm; ++i) ws_sorted.push_back(P->L[i].w);
+    std::sort(ws_sorted.begin(), ws_sorted.end(), std::greater<int32_t>());
+    size_t scratch = 0;
+    for (int32_t w : ws_sorted) {
+        bool seen = false;
+        for (int32_t v : P->shape_w) seen |= profile_shape(v) == profile_shape(w);
+        if (!seen) {
+            P->shape_w.push_back(w);
+            scratch = std::max(scratch, profile_scratch_floats(profile_slots(w), w));
+        }
+    }
     P->o_rw = o;
-    o = al(o + sizeof(float) * std::max(profile_scratch_floats(P->grid, P->wmax),
-                                        P->wsmall ? profile_scratch_floats(P->grid_small, P->wsmall) : (size_t)0));
+    o = al(o + sizeof(float) * scratch);
     P->o_counter = o;
     o = al(o + 256);
     for (int i = 0; i < nm; ++i) {
@@ -623,28 +631,29 @@ int sweep_jobs(const SweepPlan &P, char *ws, int32_t grid, ProfileJob *jobs, int
     return P.nm;
 }
 
-// The profile launches of a sweep: one persistent launch with every length,
-// or, when some lengths have a different workgroup shape from the widest, one
-// launch per shape (the grid of the second scaled like the first's).
+// The profile launches of a sweep: one persistent launch per workgroup
+// shape among the lengths, widest first, each grid scaled like the widest
+// shape's (grid of P.grid).
 hipError_t launch_sweep_profiles(const SweepPlan &P, char *ws, int32_t grid, bool dynamic, hipStream_t st,
                                  int32_t anchor) {
     ProfileJob jobs[kMaxJobs];
     const int nj = sweep_jobs(P, ws, grid, jobs, anchor);
     uint32_t *counter = (uint32_t *)(ws + P.o_counter);
     hipError_t e;
-    if (!P.wsmall) {
+    int done = 0;
+    for (int32_t wg : P.shape_w) {
+        const int32_t shape = profile_shape(wg);
+        std::stable_partition(jobs + done, jobs + nj, [&](const ProfileJob &j) { return profile_shape(j.w) == shape; });
+        int cnt = 0;
+        while (done + cnt < nj && profile_shape(jobs[done + cnt].w) == shape) ++cnt;
+        if (cnt == 0) continue;
+        const int32_t g = std::max<int32_t>(1, (int32_t)((int64_t)profile_slots(wg) * grid / P.grid));
+        for (int j = done; j < done + cnt; ++j) jobs[j].grid = g;
         if ((e = launch_fill_u32(counter, 1, 0u, st)) != hipSuccess) return e;
-        return launch_profile_batch(jobs, nj, grid, dynamic ? counter : nullptr, st);
+        if ((e = launch_profile_batch(jobs + done, cnt, g, dynamic ? counter : nullptr, st)) != hipSuccess) return e;
+        done += cnt;
     }
-    std::stable_partition(jobs, jobs + nj, [&](const ProfileJob &j) { return profile_slots(j.w) == P.grid; });
-    int nb = 0;
-    while (nb < nj && profile_slots(jobs[nb].w) == P.grid) ++nb;
-    const int32_t gs = std::max<int32_t>(1, (int32_t)((int64_t)P.grid_small * grid / P.grid));
-    for (int j = nb; j < nj; ++j) jobs[j].grid = gs;
-    if ((e = launch_fill_u32(counter, 1, 0u, st)) != hipSuccess) return e;
-    if ((e = launch_profile_batch(jobs, nb, grid, dynamic ? counter : nullptr, st)) != hipSuccess) return e;
-    if ((e = launch_fill_u32(counter, 1, 0u, st)) != hipSuccess) return e;
-    return launch_profile_batch(jobs + nb, nj - nb, gs, dynamic ? counter : nullptr, st);
+    return hipSuccess;
 }
 
 hipError_t enqueue_sweep(const SweepPlan &P, const double *T, char *ws, int32_t grid, bool dynamic,
@@ -736,8 +745,7 @@ int autotune(pst_ctx *c, const SweepPlan &P, const double *T, char *ws, TuneVal 
     HIPCHK(c, hipEventCreate(&a));
     HIPCHK(c, hipEventCreate(&b));
     TuneVal best{S, 1, 1e30f};
-    HIPCHK(c, profile_prepare(P.wmax));
-    if (P.wsmall) HIPCHK(c, profile_prepare(P.wsmall));
+    for (int32_t wg : P.shape_w) HIPCHK(c, profile_prepare(wg));
     for (const auto &cf : cand) {
         HIPCHK(c, hipEventRecord(a, c->stream));
         HIPCHK(c, launch_sweep_profiles(P, ws, cf[0], cf[1] != 0, c->stream, 0));
@@ -769,8 +777,7 @@ int run_sweep(pst_ctx *c, const SweepPlan &P, const double *T, char *ws, size_t 
         const int rc = autotune(c, P, T, ws, &cfg);
         if (rc) return rc;
     }
-    HIPCHK(c, profile_prepare(P.wmax));
-    if (P.wsmall) HIPCHK(c, profile_prepare(P.wsmall));
+    for (int32_t wg : P.shape_w) HIPCHK(c, profile_prepare(wg));
     if (!c->opt_graph) {
         HIPCHK(c, enqueue_sweep(P, T, ws, cfg.grid, cfg.dynamic != 0, c->stream, c->opt_anchor));
     } else {

@@ -71,6 +71,7 @@ hipError_t launch_profile_batch(const ProfileJob *jobs, int n, int32_t grid, uin
                                 hipStream_t st);
 int32_t profile_tile_windows(int32_t w);  // windows per tile
 int32_t profile_slots(int32_t w);                 // profile workgroups resident at once
+int32_t profile_shape(int32_t w);                 // equal for w that get the same workgroup shape
 int32_t profile_grid(int64_t tiles, int32_t w);   // persistent grid for that many tiles
 size_t profile_scratch_floats(int32_t grid, int32_t w);
 hipError_t launch_profile(const ProfileJob &job, hipStream_t st);

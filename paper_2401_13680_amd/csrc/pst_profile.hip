@@ -996,6 +996,11 @@ int32_t profile_tile_windows(int32_t w) { return geo_for(w).JT; }
 
 int32_t profile_slots(int32_t w) { return kCUs * (512 / geo_for(w).NT); }
 
+int32_t profile_shape(int32_t w) {
+    const Geo g = geo_for(w);
+    return ((g.NT / 256) << 24) | (g.V << 16) | (g.RCH << 8) | ((g.nA / 256) << 4) | (g.SBW / (32 * G));
+}
+
 int32_t profile_grid(int64_t tiles, int32_t w) {
     const int64_t slots = profile_slots(w);
     return (int32_t)(tiles < slots ? (tiles > 0 ? tiles : 1) : slots);
