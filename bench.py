@@ -6,7 +6,7 @@ greedy minimum-area snippet search, neighbours and frac (eqs. 6-8, 16-17).
 Workload: 100 000-point regime-switching series of 5 shapes, m=256, l=128,
 k=26, K=4.  cells = nseg * (m-l+1) * (n-l+1) distance-matrix entries.
 
-Prints one JSON line.  --gpus N with N > 1 is refused: this build drives one GPU.
+Prints one JSON line.  --gpus N with N > 1 is refused: the library drives one GPU.
 """
 from __future__ import annotations
 
