@@ -52,7 +52,7 @@ def measured_traffic():
     return float(fields["hbm bytes per launch"])
 
 
-def cpu_baseline(x, m, l, k, nseg_sample=3):
+def cpu_baseline(x, m, l, k, nseg_sample=20):
     """The FP64 oracle on a bounded sample of segments of the same workload."""
     import oracle
     try:
