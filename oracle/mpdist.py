@@ -107,15 +107,6 @@ def mpdist(a: np.ndarray, b: np.ndarray, l: int, k: int | None = None) -> float:
     return float(mpd(a, b, l, k)[0])
 
 
-def mpdist_in_series(x: np.ndarray, seg: int, j: int, m: int, l: int, k: int) -> float:
-    """D_seg(j) computed on its own: MPdist(S_seg, T_{j,m}).  Subsequence statistics
-    are taken over the whole series, exactly as in the full profile."""
-    Z = znorm_matrix(x, l)
-    w = m - l + 1
-    E = ed_matr(Z[seg * m: seg * m + w], Z[j: j + w])
-    return float(mpd_from_ed(E, k)[0])
-
-
 def mpdist_samples(x: np.ndarray, m: int, l: int, k: int, pairs) -> np.ndarray:
     """D_s(j) for a list of (s, j) pairs, each computed on its own from the
     w x w block of ED_matr it depends on (statistics over the whole series)."""
@@ -163,11 +154,6 @@ def profile_set(x: np.ndarray, m: int, l: int, k: int | None = None,
         E = ed_matr(Z[s * m: s * m + w], Z)                  # rows of segment s
         out.append(mpd_from_ed(E, k))
     return np.array(out)
-
-
-def profile_area(D_subset: np.ndarray) -> float:
-    """eqs. 16-17: area under M(D_subset) = element-wise minimum of the profiles."""
-    return float(np.sum(np.min(D_subset, axis=0)))
 
 
 def greedy(D: np.ndarray, K: int):

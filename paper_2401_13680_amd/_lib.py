@@ -13,6 +13,8 @@ from ctypes import POINTER, c_char_p, c_double, c_float, c_int, c_int32, c_int64
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpst.so")
+# a build whose profile kernel counts its phases (analysis only; bench.py --workload probe)
+PROBE_LIB_PATH = os.path.join(HERE, "libpst_probe.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "pst.h")
 
 PST_OK, PST_EINVAL, PST_ENOMEM, PST_EDEVICE, PST_ENOTREADY, PST_ECANCELED = 0, -1, -2, -3, -4, -5
@@ -96,7 +98,10 @@ def load():
         "pst_server_destroy": (None, [P]),
         "pst_server_last_error": (c_char_p, [P]),
         "pst_request_bytes": (c_size_t, [c_int64, c_int32, c_int32, c_int32]),
+        "pst_pool_size_class": (c_int, [c_size_t, POINTER(c_size_t)]),
+        "pst_server_batches": (c_int, [P, POINTER(ctypes.c_uint64)]),
         "pst_submit": (c_int, [P, P, c_int64, c_int32, c_int32, c_int32, POINTER(ctypes.c_uint64)]),
+        "pst_submit_device": (c_int, [P, P, c_int64, c_int32, c_int32, c_int32, POINTER(ctypes.c_uint64)]),
         "pst_poll": (c_int, [P, ctypes.c_uint64, POINTER(Snippet), c_int32, POINTER(c_double)]),
         "pst_server_drain": (c_int, [P, c_int32]),
         "pst_server_stats": (c_int, [P, POINTER(ctypes.c_uint64), POINTER(c_double), POINTER(c_int32),

@@ -49,6 +49,27 @@
 
 #include <math.h>
 
+// A build with -DPST_PROBE (build.py --probe, libpst_probe.so) measures, per
+// profile launch, the wave time of each phase and how often the selection's
+// paths run (pst_probe_read); the counters cost time and are for analysis only.
+#ifdef PST_PROBE
+// counter i is spread over 64 addresses (by lane, or by wave for the times)
+__device__ unsigned long long g_probe[32 * 64];
+#define PROBE(i, c) atomicAdd(&g_probe[(i) * 64 + (threadIdx.x & 63)], (unsigned long long)(c))
+// wave time between two marks, by lane 0 of the wave
+#define PROBE_MARK(v) const long long v = clock64()
+#define PROBE_SPAN(i, v)                                                                              \
+    do {                                                                                              \
+        if ((threadIdx.x & 63) == 0)                                                                  \
+            atomicAdd(&g_probe[(i) * 64 + ((blockIdx.x * 8 + (threadIdx.x >> 6)) & 63)],               \
+                      (unsigned long long)(clock64() - (v)));                                         \
+    } while (0)
+#else
+#define PROBE(i, c) ((void)0)
+#define PROBE_MARK(v) ((void)0)
+#define PROBE_SPAN(i, v) ((void)0)
+#endif
+
 namespace pst {
 namespace {
 
@@ -540,6 +561,7 @@ __global__ void __launch_bounds__(NT, 2) k_profile(ProfileArgs A) {
         const int64_t rb = (int64_t)s * J.row_stride;
 
         __syncthreads();  // the previous tile is done with LDS and the scratch slot
+        PROBE_MARK(tDist);
         int crow = 0;     // a constant row (h != 0) takes the general path
         for (int i = t; i < w; i += NT) {
             // y = (0.5 - h_r/2 - h_c/2) - cov * (inv_r/2) * inv_c: constant
@@ -601,6 +623,7 @@ __global__ void __launch_bounds__(NT, 2) k_profile(ProfileArgs A) {
             const int d0 = t * V - off;
             const int ub0 = d0 - (w - 1);
 
+            PROBE_MARK(tAnc);
             // 1. FP64 anchors.  The sub-tile's slice of the centred series
             //    (columns 0 .. CS+V+l-1, the query's rows 0 .. w+l+V-3) is
             //    staged in the row buffer, free until the first chunk, when it
@@ -620,6 +643,7 @@ __global__ void __launch_bounds__(NT, 2) k_profile(ProfileArgs A) {
                                 J.col.mu + C0);
             }
             lds_barrier();
+            PROBE_SPAN(17, tAnc);
 
             // register window of column statistics: slot (v + k) % V holds the
             // column of diagonal v at row k of the current chunk; row k loads
@@ -638,6 +662,7 @@ __global__ void __launch_bounds__(NT, 2) k_profile(ProfileArgs A) {
             for (int R0 = 0; R0 < w; R0 += RCH) {
                 const int nr = min(RCH, w - R0);
                 // 2. rows R0 .. R0+nr-1 of y into buf
+                PROBE_MARK(tRec);
                 const bool fast = fast_tile && R0 + RCH <= w;
                 if (act) {
                     if (fast && anchor_chunks && R0 > 0 && R0 % J.anchor_every == 0) {
@@ -724,6 +749,8 @@ __global__ void __launch_bounds__(NT, 2) k_profile(ProfileArgs A) {
                     }
                 }
                 lds_barrier();
+                PROBE_SPAN(18, tRec);
+                PROBE_MARK(tCol);
                 // 3. column minima of y (eq. 10) for the columns this sub-tile owns
                 if (nr == RCH) {
                     for (int u = t; u < own; u += NT) {
@@ -743,6 +770,8 @@ __global__ void __launch_bounds__(NT, 2) k_profile(ProfileArgs A) {
                         M.colS[u] = mn;
                     }
                 }
+                PROBE_SPAN(19, tCol);
+                PROBE_MARK(tRow);
                 // 4. sliding row minima of width w (eq. 11): each wave takes
                 //    RPW rows of the chunk, LPR lanes per row; lane al takes
                 //    the windows of block al of the sub-tile.  Columns past CS
@@ -814,6 +843,7 @@ __global__ void __launch_bounds__(NT, 2) k_profile(ProfileArgs A) {
                     }
                 }
                 lds_barrier();
+                PROBE_SPAN(20, tRow);
             }
             // column minima of the owned columns to the tile's copy
             for (int u = t; u < own; u += NT) colG[Js + u] = M.colS[u];
@@ -823,6 +853,8 @@ __global__ void __launch_bounds__(NT, 2) k_profile(ProfileArgs A) {
         //    w column minima of each window; thread a takes block a in order.
         //    Windows whose bracket misses are solved by the whole wave together.
         __syncthreads();  // the distance phase is done with LDS; colG is written
+        PROBE_SPAN(16, tDist);
+        PROBE_MARK(tSel);
         float *colY = M.colY;
         for (int u0 = t; u0 < CWT; u0 += 8 * NT) {  // eight loads in flight per thread
             float cy[8];
@@ -848,22 +880,31 @@ __global__ void __launch_bounds__(NT, 2) k_profile(ProfileArgs A) {
                 const int v = t * G + p;
                 const bool valid = v < JTe;
                 const uint32_t voff = (uint32_t)(p * pstr + t) * 4u;
+                PROBE(0, valid);
+                PROBE_MARK(tRun);
                 if (p == 0) {  // run start: the bracket from a radix select
                     uint32_t klo, khi;
+                    PROBE(1, valid);
                     lane_band<NT>(R, voff, rstr, colY + v, w, keff, r1, r2, L, klo, khi);
                     blo = klo;
                     bhi = khi - 1u;
                 }
+                PROBE_SPAN(22, tRun);
+                PROBE_MARK(tPass);
                 Bracket<NT> Bk{blo, bhi - blo, 0, 0, L};
                 window_pass(R, voff, rstr, colY + v, w, Bk);
                 const int kk = keff - Bk.below, nl = Bk.nl;
                 const bool ok = kk >= 1 && kk <= nl && nl <= CAP;
+                PROBE_SPAN(23, tPass);
+                PROBE_MARK(tSort);
+                PROBE(2, valid && ok);
                 uint32_t srt[CAP];
 #pragma unroll
                 for (int x = 0; x < CAP; ++x) srt[x] = x < nl ? L[x * NT] : 0xFFFFFFFFu;
                 sort_net(srt);
 #pragma unroll
                 for (int x = 0; x < CAP; ++x) L[x * NT] = srt[x];
+                PROBE_SPAN(24, tSort);
                 if (ok) {
                     ystar = L[(kk - 1) * NT];
                     // next bracket: ranks k-BAND .. k+BAND of this window, or
@@ -888,6 +929,7 @@ __global__ void __launch_bounds__(NT, 2) k_profile(ProfileArgs A) {
                 } else {
                     fhi = blo;
                 }
+                PROBE_MARK(tCoop);
                 uint64_t need = __ballot(valid && !ok);
                 while (need) {
                     const int ln = __ffsll((unsigned long long)need) - 1;
@@ -899,6 +941,7 @@ __global__ void __launch_bounds__(NT, 2) k_profile(ProfileArgs A) {
                     const int nc = coop_band(rw + p * pstr + tf, nA, colY + tf * G + p, w, keff, r1, r2,
                                              clo, chi, cbase, C, lane, &below);
                     if (lane == ln) {
+                        PROBE(3, 1);
                         const int kk2 = keff - below;
                         ystar = C.sorted[min(max(kk2, 1), nc) - 1];
                         blo = C.sorted[min(max(r1 - below, 1), nc) - 1];
@@ -906,6 +949,7 @@ __global__ void __launch_bounds__(NT, 2) k_profile(ProfileArgs A) {
                     }
                     wave_sync();
                 }
+                PROBE_SPAN(25, tCoop);
                 if (valid) {
                     const float dist = sqrtf(four_l * __uint_as_float(ystar));
                     J.D[(int64_t)s * J.ld + J0 + v] = dist;
@@ -914,6 +958,7 @@ __global__ void __launch_bounds__(NT, 2) k_profile(ProfileArgs A) {
             }
         }
 
+        PROBE_SPAN(21, tSel);
         // max of D over this tile (the denominator of eq. 18): one atomic per wave
         if (J.dmax_bits) {
             float mx = tmax;
@@ -1067,3 +1112,25 @@ hipError_t launch_profile(const ProfileJob &job, hipStream_t st) {
 }
 
 }  // namespace pst
+
+#ifdef PST_PROBE
+// Sums of the probe counters since the last reset: 0 windows, 1 run starts,
+// 2 windows solved by their own bracket pass, 3 cooperative selects; wave
+// cycles of 16 the distance phase, 17 FP64 anchors, 18 the FP32 recurrence,
+// 19 column minima, 20 sliding row minima, 21 the selection phase, 22 run
+// starts, 23 bracket passes, 24 sorts, 25 cooperative selects.
+extern "C" int pst_probe_read(unsigned long long *out, int reset) {
+    static unsigned long long buf[32 * 64];
+    if (hipMemcpyFromSymbol(buf, HIP_SYMBOL(g_probe), sizeof(buf)) != hipSuccess) return -3;
+    for (int i = 0; i < 32; ++i) {
+        out[i] = 0;
+        for (int j = 0; j < 64; ++j) out[i] += buf[i * 64 + j];
+    }
+    if (reset) {
+        static const unsigned long long zero[32 * 64] = {};
+        if (hipMemcpyToSymbol(HIP_SYMBOL(g_probe), zero, sizeof(zero)) != hipSuccess) return -3;
+    }
+    return 0;
+}
+#endif
+

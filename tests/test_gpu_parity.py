@@ -17,6 +17,7 @@ import pytest
 import torch
 
 import oracle
+from greedy_bounds import areas_from_profiles, check_greedy
 from paper_2401_13680_amd import api, synth
 from paper_2401_13680_amd._lib import PstError
 
@@ -91,20 +92,33 @@ def test_query_profile_matches_oracle():
 
 
 def test_snippets_four_regimes_match_golden():
+    """Snippets of the 2000-point four-regime series against the oracle, step by
+    step with the margin-aware bound (tests/greedy_bounds.py): the GPU's pick
+    must be the oracle's wherever the oracle's margin exceeds the bound that the
+    profile differences put on the areas.  ProfileArea after each pick equals
+    an FP64 recompute from the GPU's own returned profiles."""
     gold = json.load(open(os.path.join(GOLDEN, "snippets_four_regimes_n2000.json")))
     x = synth.four_regimes(1).x
-    r = api.snippets(dev(x), gold["m"], gold["l"], gold["K"], gold["k"], profiles=True, owner=True)
-    segs = [rec["segment"] for rec in r["records"]]
-    assert segs == [rec["segment"] for rec in gold["records"]]
-    assert [rec["greedy_rank"] for rec in r["records"]] == [rec["greedy_rank"] for rec in gold["records"]]
-    for a, b in zip(r["records"], gold["records"]):
-        assert a["frac"] == b["frac"]
-        # ProfileArea sums n-m+1 FP32 profile entries, many of them near zero
-        # where the square root amplifies FP32 rounding of rho: 1e-3 relative
-        assert abs(a["area_after"] - b["area_after"]) <= 1e-3 * b["area_after"]
-    own = r["owner"].cpu().numpy()
-    counts = [int(np.count_nonzero(own == p)) for p in range(gold["K"])]
-    assert counts == gold["counts"]
+    m, l, k, K = gold["m"], gold["l"], gold["k"], gold["K"]
+    r = api.snippets(dev(x), m, l, K, k, profiles=True, owner=True)
+    D, _ = api.profile_set(dev(x), m, l, k)
+    Dg = D.cpu().numpy().astype(np.float64)
+    Dr = oracle.profile_set(x, m, l, k)
+    by_rank = sorted(r["records"], key=lambda rec: rec["greedy_rank"])
+    picks = [rec["segment"] for rec in by_rank]
+    res = check_greedy(picks, {s: Dg[s] for s in range(len(Dg))}, {s: Dr[s] for s in range(len(Dr))},
+                       list(range(len(Dr))), "four_regimes")
+    for (margin, B, _), gm in zip(res, gold["margins"]):
+        assert margin == pytest.approx(gm, rel=1e-9)
+    prof = r["profiles"].cpu().numpy()
+    np.testing.assert_array_equal(prof, D.cpu().numpy()[picks])
+    np.testing.assert_allclose([rec["area_after"] for rec in by_rank], areas_from_profiles(prof), rtol=1e-12)
+    if picks == gold["picks"]:
+        for a, b in zip(r["records"], gold["records"]):
+            assert (a["segment"], a["greedy_rank"], a["frac"]) == (b["segment"], b["greedy_rank"], b["frac"])
+        own = r["owner"].cpu().numpy()
+        counts = [int(np.count_nonzero(own == p)) for p in range(K)]
+        assert counts == gold["counts"]
     assert abs(r["dmax"] - gold["dmax"]) <= 1e-4 * gold["dmax"]
 
 
@@ -175,7 +189,8 @@ def test_deterministic():
 def test_full_size_sampled_and_snippets():
     """The 100k-point, m=256 workload at full size: sampled profile entries
     against the oracle one by one, and the snippets against the stored oracle
-    result."""
+    result with the margin-aware bound, computed from the oracle's rows of the
+    picks and runners-up of every step."""
     gold = json.load(open(os.path.join(GOLDEN, "snippets_regimes5_n100000.json")))
     x = synth.regime_series(100_000, 2, synth.SHAPES5).x
     m, l, k, K = gold["m"], gold["l"], gold["k"], gold["K"]
@@ -189,10 +204,21 @@ def test_full_size_sampled_and_snippets():
     got = np.array([Dg[s, j] for s, j in pairs])
     assert_profiles_close(got, ref, l, "full-size samples")
     assert abs(float(dmax.item()) - gold["dmax"]) <= 1e-4 * gold["dmax"]
-    r = api.snippets(dev(x), m, l, K, k)
-    assert [rec["segment"] for rec in r["records"]] == [rec["segment"] for rec in gold["records"]]
-    for a, b in zip(r["records"], gold["records"]):
-        assert abs(a["frac"] - b["frac"]) <= 1e-3
+    r = api.snippets(dev(x), m, l, K, k, profiles=True)
+    by_rank = sorted(r["records"], key=lambda rec: rec["greedy_rank"])
+    picks = [rec["segment"] for rec in by_rank]
+    cands = sorted(set(gold["picks"]) | set(gold["runners"]) | set(picks))
+    print(f"full size: oracle rows of segments {cands}", flush=True)
+    Dr = oracle.profile_set(x, m, l, k, segments=cands)
+    rows_r = {s: Dr[i] for i, s in enumerate(cands)}
+    rows_g = {s: Dg[s].astype(np.float64) for s in cands}
+    res = check_greedy(picks, rows_g, rows_r, cands, "regimes5_n100000")
+    assert picks == gold["picks"] or not all(eq for _, _, eq in res)
+    prof = r["profiles"].cpu().numpy()
+    np.testing.assert_allclose([rec["area_after"] for rec in by_rank], areas_from_profiles(prof), rtol=1e-12)
+    if picks == gold["picks"]:
+        for a, b in zip(r["records"], gold["records"]):
+            assert a["segment"] == b["segment"] and abs(a["frac"] - b["frac"]) <= 1e-3
 
 
 def _sweep_key(r):

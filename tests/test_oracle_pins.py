@@ -216,3 +216,18 @@ def test_local_pairs_equal_full_profile():
     pairs = [(int(rng.integers(D.shape[0])), int(rng.integers(D.shape[1]))) for _ in range(30)]
     got = oracle.mpdist_pairs_local(x, m, l, k, pairs)
     np.testing.assert_allclose(got ** 2, [D[s, j] ** 2 for s, j in pairs], atol=1e-9)
+
+
+def test_samples_equal_full_profile():
+    """mpdist_samples (each entry from its own w x w block of ED_matr, the
+    checker of the full-size GPU test) equals the whole profile set entry for
+    entry, including the first and last segment and window."""
+    x = synth.regime_series(3000, 18, len_range=(300, 900)).x
+    m, l, k = 60, 30, 6
+    D = oracle.profile_set(x, m, l, k)
+    rng = np.random.default_rng(2)
+    nseg, Nm = D.shape
+    pairs = [(int(rng.integers(nseg)), int(rng.integers(Nm))) for _ in range(40)]
+    pairs += [(0, 0), (nseg - 1, Nm - 1), (nseg - 1, 0), (0, Nm - 1), (7, 7 * m)]
+    got = oracle.mpdist_samples(x, m, l, k, pairs)
+    np.testing.assert_array_equal(got, [D[s, j] for s, j in pairs])
