@@ -1,10 +1,20 @@
-"""Benchmark: MPdist distance-matrix cells per second on one MI355X.
+"""Benchmark: MPdist distance-matrix cells per second on one MI355X, with
+p50/p99 request latency.
 
-One step = the whole snippet-finding hot path on one series, resident in HBM:
-FP64 window statistics, the MPdist profile of every segment (eqs. 9-15), the
-greedy minimum-area snippet search, neighbours and frac (eqs. 6-8, 16-17).
-Workload: 100 000-point regime-switching series of 5 shapes, m=256, l=128,
-k=26, K=4.  cells = nseg * (m-l+1) * (n-l+1) distance-matrix entries.
+Default workload (the metric's own): the serving stream of regime-switching
+series, Poisson arrivals at 20 requests/s, n log-uniform in [1e4, 5e5], m
+uniform in {64, 128, 256, 512, 1024}, l = m/2, K uniform in 3..5.  A step is
+ten requests of the stream, so --steps 20 serves the 200-request stream.
+Inputs are resident in HBM (pst_submit_device) when the timed region starts.
+`value` = distance-matrix cells of the stream / time to serve all of it
+submitted at once (continuous batching); the plain per-request path
+(pst_snippets one request after another) is measured beside it; p50/p99 come
+from a replay at the stream's own arrival times.
+cells = nseg * (m-l+1) * (n-l+1) per request.
+
+--workload plain: one 100 000-point five-shape series, m=256, l=128, K=4, the
+whole snippet search per step.  Other workloads: sweep, multi, schedule,
+blocked, probe.
 
 Prints one JSON line.  --gpus N with N > 1 is refused: the library drives one GPU.
 """
@@ -29,16 +39,18 @@ OPS_PER_CELL = 8
 PEAK_LANE_OPS = 256 * 64 * 2.4e9
 
 
-TRAFFIC_NOTE = os.path.join(ROOT, "profiles", "k_profile_regimes5_n100000_traffic.md")
-KERNEL_SRC = os.path.join(ROOT, "paper_2401_13680_amd", "csrc", "pst_profile.hip")
+TRAFFIC_NOTE = os.path.join(ROOT, "profiles", "k_profile_traffic.md")
+KERNEL_HASH = os.path.join(ROOT, "paper_2401_13680_amd", "libpst.k_profile.sha256")
 
 
-def measured_traffic():
-    """HBM bytes per profile launch from the committed FETCH_SIZE / WRITE_SIZE
-    measurement, or None once the kernel source differs from the one measured."""
-    import hashlib
+def measured_traffic(cells_per_launch):
+    """HBM bytes per profile launch: the committed FETCH_SIZE + WRITE_SIZE
+    measurement (bytes per distance-matrix cell, copy-calibrated) times the
+    launch's cells, or None once the profile kernel's machine code differs from
+    the one measured (hash written by the build)."""
     try:
         note = open(TRAFFIC_NOTE).read()
+        built = open(KERNEL_HASH).read().strip()
     except OSError:
         return None
     fields = {}
@@ -46,10 +58,9 @@ def measured_traffic():
         if ":" in line and line.startswith("- "):
             key, _, val = line[2:].partition(":")
             fields[key.strip()] = val.strip().strip("`")
-    sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
-    if fields.get("kernel source sha256") != sha or "hbm bytes per launch" not in fields:
+    if fields.get("k_profile code sha256") != built or "hbm bytes per cell" not in fields:
         return None
-    return float(fields["hbm bytes per launch"])
+    return float(fields["hbm bytes per cell"]) * cells_per_launch
 
 
 def cpu_baseline(x, m, l, k, nseg_sample=20):
@@ -72,6 +83,43 @@ def cpu_baseline(x, m, l, k, nseg_sample=20):
     return dict(value=cells / dt, unit="cells/s", cores=1, kind="oracle",
                 sample=f"profiles of {len(segs)} of {n // m} segments ({cells:.3g} cells, "
                        f"{dt:.1f} s), numpy FP64, BLAS limited to 1 thread")
+
+
+PROBE_NAMES = {0: "windows", 1: "run_starts", 2: "windows_by_own_pass", 3: "cooperative_selects"}
+PROBE_PHASES = {16: "distance phase", 17: "  FP64 anchors", 18: "  FP32 recurrence", 19: "  column minima",
+                20: "  sliding row minima", 21: "selection phase", 22: "  run starts (radix select)",
+                23: "  bracket passes", 24: "  sorts", 25: "  cooperative selects"}
+
+
+def probe_bench(args):
+    """Phase split of the profile kernel on the 100 000-point workload from the
+    probe build (libpst_probe.so, built by `python -m paper_2401_13680_amd.build
+    --probe`): wave cycles per phase and how often the selection's paths run.
+    The probe's own atomics slow the kernel; the split, not the time, is the
+    result."""
+    import ctypes
+
+    import torch
+
+    from paper_2401_13680_amd import _lib, api, synth
+
+    _lib.LIB_PATH = _lib.PROBE_LIB_PATH
+    L = _lib.load()
+    L.pst_probe_read.argtypes = [ctypes.POINTER(ctypes.c_ulonglong), ctypes.c_int]
+    buf = (ctypes.c_ulonglong * 32)()
+    n, m, l, K = WORKLOAD["n"], WORKLOAD["m"], WORKLOAD["l"], WORKLOAD["K"]
+    T = torch.from_numpy(synth.workload_series(WORKLOAD["name"])).cuda()
+    api.profile_set(T, m, l)
+    torch.cuda.synchronize()
+    L.pst_probe_read(buf, 1)
+    api.profile_set(T, m, l)
+    torch.cuda.synchronize()
+    L.pst_probe_read(buf, 1)
+    tot = buf[16] + buf[21]
+    out = dict(workload=WORKLOAD["name"], counts={v: int(buf[k]) for k, v in PROBE_NAMES.items()},
+               wave_cycles={v.strip(): int(buf[k]) for k, v in PROBE_PHASES.items()},
+               share_of_wave_time={v.strip(): round(buf[k] / tot, 4) for k, v in PROBE_PHASES.items()})
+    print(json.dumps(out), flush=True)
 
 
 def sweep_bench(args):
@@ -267,56 +315,196 @@ def blocked_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def _cpu_task(args):
+    import numpy as np
+    import oracle
+    x, m, l, s = args
+    t0 = time.perf_counter()
+    oracle.profile_set(np.asarray(x), m, l, None, segments=[s])
+    return time.perf_counter() - t0
+
+
+def cpu_baseline_serving(reqs, per_m=4, n_max=150_000):
+    """The FP64 oracle on a bounded sample of the serving stream: the middle
+    segment of the first `per_m` requests of each m with n <= n_max, on a
+    process pool over every host core, and three of them on one core."""
+    import platform
+    from multiprocessing import get_context
+
+    try:
+        from threadpoolctl import threadpool_limits
+        threadpool_limits(limits=1)
+    except Exception:  # pragma: no cover
+        pass
+    cores = len(os.sched_getaffinity(0))
+    tasks, seen = [], {}
+    for r in reqs:
+        if len(r.x) <= n_max and seen.get(r.m, 0) < per_m:
+            seen[r.m] = seen.get(r.m, 0) + 1
+            tasks.append((r.x, r.m, r.l, (len(r.x) // r.m) // 2))
+    cells = [(len(x) - l + 1) * (m - l + 1) for x, m, l, _ in tasks]
+    env = dict(OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    old = {k: os.environ.get(k) for k in env}
+    os.environ.update(env)
+    try:
+        with get_context("spawn").Pool(min(cores, len(tasks))) as pool:
+            t0 = time.perf_counter()
+            pool.map(_cpu_task, tasks, chunksize=1)
+            wall = time.perf_counter() - t0
+        one = [_cpu_task(t) for t in tasks[:3]]
+    finally:
+        for k, v in old.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+    try:
+        model = [ln.split(":", 1)[1].strip() for ln in open("/proc/cpuinfo") if ln.startswith("model name")][0]
+    except Exception:  # pragma: no cover
+        model = platform.processor()
+    return dict(value=sum(cells) / wall, unit="cells/s", cores=min(cores, len(tasks)), kind="oracle",
+                sample=f"profile of the middle segment of {len(tasks)} requests of the stream ({per_m} per m, "
+                       f"n <= {n_max}; {sum(cells):.3g} cells, {wall:.1f} s) on a process pool, numpy FP64, "
+                       f"BLAS 1 thread per process",
+                one_core=dict(value=sum(cells[:3]) / sum(one), unit="cells/s",
+                              sample=f"3 of those segments, {sum(one):.1f} s"),
+                host=dict(nproc=os.cpu_count(), affinity=cores, cpu=model))
+
+
 def serve_bench(args):
-    """Serving: Poisson arrivals (20 / s) of regime-switching series with n
-    log-uniform in [1e4, 5e5], m in {64, .., 1024}, l = m/2, K in 3..5."""
+    """The serving stream (the metric's workload): Poisson arrivals (20/s) of
+    regime-switching series, n log-uniform in [1e4, 5e5], m in {64, .., 1024},
+    l = m/2, K in 3..5; ten requests per step."""
+    import ctypes
+
+    import numpy as np
+    import torch
+
+    from paper_2401_13680_amd import api, synth
+
+    nreq = 10 * args.steps
+    reqs = synth.poisson_requests(num=nreq, rate=20.0, seed=5)
+    warm = synth.poisson_requests(num=10 * args.warmup, rate=20.0, seed=105) if args.warmup > 0 else []
+    cells_of = lambda r: (len(r.x) // r.m) * (r.m - r.l + 1) * (len(r.x) - r.l + 1)
+    cells = sum(cells_of(r) for r in reqs)
+    Ts = [torch.from_numpy(r.x).cuda() for r in reqs]
+    Tw = [torch.from_numpy(r.x).cuda() for r in warm]
+    torch.cuda.synchronize()
+    budget, slots = 160 << 30, 32
+    if args.plain_only:  # the plain pass alone (for hardware-counter runs of its profile launches)
+        for T, r in zip(Ts, reqs):
+            api.snippets(T, r.m, r.l, r.K)
+        torch.cuda.synchronize()
+        print(json.dumps(dict(workload=f"poisson20_serving_{nreq}", plain_only=True, cells=cells,
+                              profile_launches=nreq)), flush=True)
+        return
+
+    def serve_all(srv, series, rs):
+        tk = [srv.submit(T, r.m, r.l, r.K) for T, r in zip(series, rs)]
+        srv.drain()
+        return [srv.poll(t) for t in tk]
+
+    srv = api.Server(0, hbm_budget_bytes=budget, max_slots=slots)
+    if warm:
+        serve_all(srv, Tw, warm)
+    b0 = srv.stats()["batches"]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    served = serve_all(srv, Ts, reqs)
+    sat = time.perf_counter() - t0
+    nbatch = srv.stats()["batches"] - b0
+    assert all(r["status"] == 0 for r in served)
+
+    # plain: pst_snippets one request after another, the profile kernel timed
+    # by the library's events around each launch
+    ctx = api.context(0)
+    L = ctx.L
+    for T, r in zip(Tw[:3], warm[:3]):
+        api.snippets(T, r.m, r.l, r.K, ctx=ctx)
+    torch.cuda.synchronize()
+    L.pst_set_timing(ctx.h, 1)
+    kms, ms = [], ctypes.c_float()
+    t0 = time.perf_counter()
+    plain_recs = []
+    for T, r in zip(Ts, reqs):
+        plain_recs.append(api.snippets(T, r.m, r.l, r.K, ctx=ctx)["records"])
+        ctx.check(L.pst_last_profile_ms(ctx.h, ctypes.byref(ms)))
+        kms.append(ms.value)
+    torch.cuda.synchronize()
+    plain = time.perf_counter() - t0
+    L.pst_set_timing(ctx.h, 0)
+    same = all(a["records"] == b for a, b in zip(served, plain_recs))
+
+    # latency: the stream replayed at its own arrival times
+    t0 = time.perf_counter()
+    tickets = []
+    for T, r in zip(Ts, reqs):
+        delay = r.arrival_s - (time.perf_counter() - t0)
+        if delay > 0:
+            time.sleep(delay)
+        tickets.append(srv.submit(T, r.m, r.l, r.K))
+    srv.drain()
+    span = time.perf_counter() - t0
+    lat = [srv.poll(t)["latency_ms"] for t in tickets]
+    srv.close()
+
+    # the same stream submitted from host memory (PCIe copies included)
+    srv = api.Server(0, hbm_budget_bytes=budget, max_slots=slots)
+    t0 = time.perf_counter()
+    serve_all(srv, [r.x for r in reqs], reqs)
+    host_sat = time.perf_counter() - t0
+    srv.close()
+
+    k_ms = float(np.sum(kms))
+    achieved = OPS_PER_CELL * cells / (k_ms * 1e-3) / 1e12
+    peak = PEAK_LANE_OPS / 1e12
+    offered = cells / reqs[-1].arrival_s
+    out = dict(metric="MPdist distance-matrix cells/sec on 1 MI355X; p50/p99 request latency",
+               value=cells / sat, unit="cells/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
+               ms_per_step=sat * 1e3 / args.steps, higher_is_better=True, scaling="weak", vs_baseline=None,
+               dtype="f32", data="synthetic",
+               config=dict(workload=f"poisson20_serving_{nreq}", requests=nreq, requests_per_step=10,
+                           n="log-uniform [1e4, 5e5]", m=[64, 128, 256, 512, 1024], l="m/2", K="3..5",
+                           rate_per_s=20.0, cells=cells,
+                           step="ten requests of the stream, all submitted at once with series in HBM, "
+                                "served with continuous batching"),
+               latency_ms=dict(p50=float(np.percentile(lat, 50)), p99=float(np.percentile(lat, 99)),
+                               mean=float(np.mean(lat)), replay_s=span,
+                               offered_cells_per_s=offered,
+                               offered_over_capacity=offered / (cells / sat)),
+               plain_one_request_at_a_time=dict(value=cells / plain, seconds=plain),
+               served_over_plain=plain / sat, served_equals_plain=same, batches=nbatch,
+               host_submit_pcie_inclusive=dict(value=cells / host_sat, seconds=host_sat),
+               roofline=dict(bound="alu", achieved=achieved, peak=peak, unit="Tops/s (VALU lane-ops)",
+                             frac=achieved / peak, traffic=measured_traffic(cells_per_launch=cells / nreq),
+                             kernel="k_profile", kernel_ms=k_ms / nreq, launches=nreq,
+                             ops_per_cell=OPS_PER_CELL,
+                             note="profile launches of the plain pass over the same requests, "
+                                  "HIP events around each launch"))
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_serving(reqs)
+    print(json.dumps(out), flush=True)
+
+
+def serve_order_bench(args):
+    """Admission order under queueing: the serving stream replayed with two
+    slots, in arrival order and shortest predicted first (run-time model of
+    section 4.2 seeded with the plain per-request times)."""
     import numpy as np
     import torch
 
     from paper_2401_13680_amd import api, synth
 
     reqs = synth.poisson_requests(num=args.requests, rate=20.0, seed=5)
-    cells = sum((len(r.x) // r.m) * (r.m - r.l + 1) * (len(r.x) - r.l + 1) for r in reqs)
-    # plain: one request after another with pst_snippets
     Ts = [torch.from_numpy(r.x).cuda() for r in reqs]
     api.snippets(Ts[0], reqs[0].m, reqs[0].l, reqs[0].K)
-    torch.cuda.synchronize()
-    plain_ms = []
-    t0 = time.perf_counter()
+    model = api.RuntimeModel(2)
     for r, T in zip(reqs, Ts):
+        torch.cuda.synchronize()
         t1 = time.perf_counter()
         api.snippets(T, r.m, r.l, r.K)
         torch.cuda.synchronize()
-        plain_ms.append((time.perf_counter() - t1) * 1e3)
-    plain = time.perf_counter() - t0
-    del Ts
-    srv = api.Server(0, hbm_budget_bytes=96 << 30, max_slots=8)
-    # saturation replay: everything submitted at once
-    t0 = time.perf_counter()
-    tk = [srv.submit(r.x, r.m, r.l, r.K) for r in reqs]
-    srv.drain()
-    sat = time.perf_counter() - t0
-    for t in tk:
-        srv.poll(t)
-    # Poisson replay at the recorded arrival times
-    t0 = time.perf_counter()
-    tickets, lat = [], []
-    for r in reqs:
-        delay = r.arrival_s - (time.perf_counter() - t0)
-        if delay > 0:
-            time.sleep(delay)
-        tickets.append(srv.submit(r.x, r.m, r.l, r.K))
-    srv.drain()
-    span = time.perf_counter() - t0
-    for t in tickets:
-        lat.append(srv.poll(t)["latency_ms"])
-    srv.close()
-    # admission order under queueing (two slots, so requests wait): the same
-    # Poisson replay in arrival order and shortest predicted first, the model
-    # seeded with the plain pass's per-request times
-    model = api.RuntimeModel(2)
-    for r, ms in zip(reqs, plain_ms):
-        model.observe(len(r.x), r.m, r.l, ms)
+        model.observe(len(r.x), r.m, r.l, (time.perf_counter() - t1) * 1e3)
     model.fit()
     order = {}
     for name, pol in (("arrival", api.Server.ARRIVAL), ("shortest_predicted_first", api.Server.SHORTEST_PREDICTED)):
@@ -324,41 +512,31 @@ def serve_bench(args):
         srv.set_policy(pol, model if pol else None)
         t0 = time.perf_counter()
         tickets = []
-        for r in reqs:
+        for T, r in zip(Ts, reqs):
             delay = r.arrival_s - (time.perf_counter() - t0)
             if delay > 0:
                 time.sleep(delay)
-            tickets.append(srv.submit(r.x, r.m, r.l, r.K))
+            tickets.append(srv.submit(T, r.m, r.l, r.K))
         srv.drain()
         sp = time.perf_counter() - t0
         lt = [srv.poll(t)["latency_ms"] for t in tickets]
         srv.close()
         order[name] = dict(seconds=round(sp, 4), p50=round(float(np.percentile(lt, 50)), 2),
                            p99=round(float(np.percentile(lt, 99)), 2), mean=round(float(np.mean(lt)), 2))
-    out = dict(metric="MPdist distance-matrix cells/sec on 1 MI355X; p50/p99 request latency",
-               value=cells / sat, unit="cells/s", n_gpus=1, steps=1, warmup=1,
-               ms_per_step=sat * 1e3, higher_is_better=True, scaling="weak", vs_baseline=None,
-               dtype="f32", data="synthetic",
-               config=dict(workload="poisson20_regimes_serving", requests=len(reqs), cells=cells,
-                           step="all requests submitted at once, served with overlap"),
-               latency_ms=dict(p50=float(np.percentile(lat, 50)), p99=float(np.percentile(lat, 99)),
-                               mean=float(np.mean(lat))),
-               poisson_replay=dict(seconds=span, cells_per_s=cells / span),
-               admission_order_two_slots=order,
-               plain_one_request_at_a_time=dict(value=cells / plain, seconds=plain),
-               served_over_plain=plain / sat)
-    print(json.dumps(out), flush=True)
+    print(json.dumps(dict(workload=f"poisson20_serving_{len(reqs)}_two_slots", admission_order=order)), flush=True)
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="regimes5_n100000",
-                    choices=["regimes5_n100000", "sweep", "serve", "multi", "schedule", "blocked"])
-    ap.add_argument("--requests", type=int, default=40, help="serve: number of requests")
+    ap.add_argument("--workload", default="serve",
+                    choices=["serve", "plain", "serve_order", "sweep", "multi", "schedule", "blocked", "probe"])
+    ap.add_argument("--requests", type=int, default=40, help="serve_order: number of requests")
+    ap.add_argument("--plain-only", action="store_true",
+                    help="serve: only the plain per-request pass (one profile launch per request)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="end with one 1 GiB device copy (reference for FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
@@ -369,12 +547,16 @@ def main():
         return sweep_bench(args)
     if args.workload == "serve":
         return serve_bench(args)
+    if args.workload == "serve_order":
+        return serve_order_bench(args)
     if args.workload == "multi":
         return multi_bench(args)
     if args.workload == "schedule":
         return schedule_bench(args)
     if args.workload == "blocked":
         return blocked_bench(args)
+    if args.workload == "probe":
+        return probe_bench(args)
 
     import numpy as np
     import torch
@@ -424,7 +606,7 @@ def main():
                     step="stats + all segment profiles + greedy + neighbours"),
         latency_ms=dict(p50=float(np.percentile(lat, 50)), p99=float(np.percentile(lat, 99))),
         roofline=dict(bound="alu", achieved=achieved, peak=peak, unit="Tops/s (VALU lane-ops)",
-                      frac=achieved / peak, traffic=measured_traffic(), kernel="k_profile",
+                      frac=achieved / peak, traffic=measured_traffic(cells), kernel="k_profile",
                       kernel_ms=k_ms, ops_per_cell=OPS_PER_CELL),
     )
     if args.calibrate_copy:

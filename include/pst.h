@@ -241,26 +241,48 @@ int  pst_partition_lengths(const pst_model *model, int64_t n, const int32_t *m_l
 
 /* ---- Serving ----
  * A server admits requests (one series each, with its own n, m, l, K) as
- * device memory and slots free up, runs each admitted request's whole
- * pipeline (statistics, profiles, greedy search, neighbours) on its own
- * stream so that requests overlap on the device, and keeps each result until
- * it is collected.  Admission: first fit in arrival order while the sum of the
- * admitted requests' footprints (pst_request_bytes) stays within
- * hbm_budget_bytes and at most max_slots (1..64) run at once.  The server owns
- * its device memory (cached between requests) and a worker thread.  All
- * pst_server functions are thread-safe.  A request's result equals that of
- * pst_snippets on the same input (k is the default of m). */
+ * device memory and slots free up and keeps each result until it is
+ * collected (section 4.2 runs many lengths of one series across a cluster;
+ * here many series share one GPU).  Work is batched continuously: an admitted
+ * request's copy-in and statistics run on a preparation stream; the profile
+ * tiles of all ready requests of one workgroup shape (up to 16) run in one
+ * shared persistent launch, a new batch starting on a second stream while the
+ * previous one drains; each request's greedy search, neighbours and result
+ * copies follow its batch.  Admission: first fit in arrival order while the
+ * admitted requests' footprints (pst_request_bytes, rounded up to the
+ * server's 25 % size classes) plus the profile scratch of the two batch
+ * streams stay within hbm_budget_bytes, and at most max_slots (1..64)
+ * requests are admitted at once.  The server owns its device memory (freed
+ * blocks are cached up to a quarter of the budget; an allocation that fails
+ * drops the cache and tries once more) and a worker thread.  A request whose
+ * memory cannot be allocated while nothing else holds memory completes with
+ * PST_ENOMEM; after a device error every admitted request completes with
+ * PST_EDEVICE and the server accepts no more.  All pst_server functions are
+ * thread-safe.  A request's result equals that of pst_snippets on the same
+ * input (k is the default of m), whatever it is batched with. */
 typedef struct pst_server pst_server;
 int pst_server_create(pst_server **out, int device, size_t hbm_budget_bytes, int32_t max_slots);
 void pst_server_destroy(pst_server *server);   /* drops requests not yet admitted */
 const char *pst_server_last_error(const pst_server *server);
-/* Device bytes one request holds while admitted (0 if the sizes are invalid). */
+/* Device bytes one request holds while admitted, before rounding to a size
+ * class: the series and its workspace without profile scratch (0 if the sizes
+ * are invalid). */
 size_t pst_request_bytes(int64_t n, int32_t m, int32_t l, int32_t K);
+/* Host-only: the size class (bytes) the server charges for a request of
+ * `bytes` (the smallest 1 MiB * 1.25^j not below it). */
+int pst_pool_size_class(size_t bytes, size_t *charged);
 /* Queue a request; T_host (n values) is copied before return.  PST_EINVAL for
- * invalid sizes, PST_ENOMEM if the request can never fit the budget,
- * PST_EDEVICE after a device error. */
+ * invalid sizes, PST_ENOMEM if the request with the profile scratch of a
+ * batch of its own width can never fit the budget, PST_EDEVICE after a device
+ * error. */
 int pst_submit(pst_server *server, const double *T_host, int64_t n, int32_t m, int32_t l, int32_t K,
                uint64_t *ticket);
+/* As pst_submit with the series already in device memory of the server's
+ * device (T_dev, n doubles, owned by the caller): the server copies it on the
+ * device once the request is admitted, so T_dev must stay valid and unchanged
+ * until pst_poll returns the request's status. */
+int pst_submit_device(pst_server *server, const double *T_dev, int64_t n, int32_t m, int32_t l, int32_t K,
+                      uint64_t *ticket);
 /* PST_ENOTREADY until the request is done; then fills out_host[K] (ordered
  * as pst_snippets), the latency from submission to completion in ms, releases
  * the ticket and returns its status (PST_EINVAL for a non-finite series). */
@@ -284,6 +306,8 @@ enum { PST_POLICY_ARRIVAL = 0, PST_POLICY_SHORTEST_PREDICTED = 1 };
 int pst_server_set_policy(pst_server *server, int32_t policy, const pst_model *seed);
 int pst_server_stats(pst_server *server, uint64_t *completed, double *cells, int32_t *active,
                      size_t *bytes_in_use);
+/* Profile batches launched so far. */
+int pst_server_batches(pst_server *server, uint64_t *batches);
 /* Host-only simulation of the admission policy (no device use), for tests:
  * request i of `bytes[i]` arrives at arrive_ms[i] (non-decreasing) and holds
  * its memory for service_ms[i] after admission; start_ms[i] receives its

@@ -310,10 +310,16 @@ def label_f1(owner, truth, m: int, K: int, C: int, ctx: Context | None = None):
     return dict(map=list(mp), precision=list(prec), recall=list(rec), f1=list(f1), macro_f1=macro.value)
 
 
+def torch_tensor_type():
+    import torch
+    return torch.Tensor
+
+
 class Server:
     """Request server of the library (pst_server_*): admission by device-memory
-    footprint and slots, one stream per running request, results kept until
-    polled.  Series are host numpy float64 arrays; each is copied on submit."""
+    footprint and slots, continuous batching of the admitted requests' profile
+    tiles into shared launches, results kept until polled.  Series are host
+    numpy float64 arrays; each is copied on submit."""
 
     def __init__(self, device: int = 0, hbm_budget_bytes: int = 64 << 30, max_slots: int = 8):
         self.L = _lib.load()
@@ -323,12 +329,22 @@ class Server:
             raise PstError(rc, "pst_server_create failed")
         self.h = h
         self.K = {}
+        self._keep = {}   # device series of requests not yet collected
 
     def submit(self, x, m: int, l: int, K: int) -> int:
-        import numpy as np
-        x = np.ascontiguousarray(x, dtype=np.float64)
+        """Queue series x: a host numpy array (copied now), or a CUDA float64
+        tensor on the server's device, which must stay alive and unchanged
+        until poll() returns the request's result."""
         t = ctypes.c_uint64()
-        rc = self.L.pst_submit(self.h, c_void_p(x.ctypes.data), len(x), m, l, K, byref(t))
+        if isinstance(x, torch_tensor_type()):
+            if not x.is_cuda or x.dtype != __import__("torch").float64 or not x.is_contiguous():
+                raise ValueError("device series must be a contiguous CUDA float64 tensor")
+            rc = self.L.pst_submit_device(self.h, c_void_p(x.data_ptr()), x.numel(), m, l, K, byref(t))
+            self._keep[t.value] = x
+        else:
+            import numpy as np
+            x = np.ascontiguousarray(x, dtype=np.float64)
+            rc = self.L.pst_submit(self.h, c_void_p(x.ctypes.data), len(x), m, l, K, byref(t))
         if rc != 0:
             raise PstError(rc, self.L.pst_server_last_error(self.h).decode())
         self.K[t.value] = K
@@ -343,6 +359,7 @@ class Server:
         if rc == _lib.PST_ENOTREADY:
             return None
         del self.K[ticket]
+        self._keep.pop(ticket, None)
         return dict(status=rc, records=_records(recs, K) if rc == 0 else None, latency_ms=lat.value)
 
     def drain(self, timeout_ms: int = 600_000):
@@ -362,7 +379,10 @@ class Server:
     def stats(self):
         c, cells, a, b = ctypes.c_uint64(), c_double(), c_int32(), ctypes.c_size_t()
         self.L.pst_server_stats(self.h, byref(c), byref(cells), byref(a), byref(b))
-        return dict(completed=c.value, cells=cells.value, active=a.value, bytes_in_use=b.value)
+        nb = ctypes.c_uint64()
+        self.L.pst_server_batches(self.h, byref(nb))
+        return dict(completed=c.value, cells=cells.value, active=a.value, bytes_in_use=b.value,
+                    batches=nb.value)
 
     def close(self):
         if getattr(self, "h", None):

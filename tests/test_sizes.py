@@ -29,7 +29,28 @@ def test_sizes_grow_with_the_problem():
     a = L.pst_workspace_bytes(100_000, 256, 128, 4)
     b = L.pst_workspace_bytes(200_000, 256, 128, 4)
     assert 0 < a < b
-    assert L.pst_request_bytes(100_000, 256, 128, 4) >= a + 8 * 100_000
+    # a server request holds the series and the workspace without the profile
+    # scratch (batches share one scratch per batch stream): at least the profile
+    # set and the series, less than the standalone workspace
+    r = L.pst_request_bytes(100_000, 256, 128, 4)
+    nseg, Nm = 100_000 // 256, 100_000 - 256 + 1
+    assert 4 * nseg * Nm + 8 * 100_000 <= r < a + 8 * 100_000
+
+
+def test_pool_size_classes():
+    import ctypes
+    got = ctypes.c_size_t()
+    prev = 0
+    for b in (1, 1 << 20, (1 << 20) + 1, 3 << 20, 1 << 30, 123456789):
+        assert L.pst_pool_size_class(b, ctypes.byref(got)) == 0
+        c = got.value
+        assert c >= b and c >= 1 << 20
+        assert c <= max(1 << 20, int(b * 1.25) + 1)     # classes 25 % apart
+    # the same class for every size inside it
+    L.pst_pool_size_class(5 << 20, ctypes.byref(got))
+    c = got.value
+    L.pst_pool_size_class(c, ctypes.byref(got))
+    assert got.value == c
 
 
 def test_blocked_block_search():
