@@ -98,6 +98,23 @@ int pst_mpdist_profile(pst_ctx *ctx, const double *T_dev, int64_t n,
                        const double *Q_dev, int32_t m, int32_t l, int32_t k,
                        float *out_dev, void *ws_dev, size_t ws_bytes);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the eq. 14
+ * query profile of pst_mpdist_profile without a workspace argument.  Its
+ * scratch is a fixed 256 MiB device array of the library, one per GPU the
+ * library runs on, held until the process ends; the call allocates nothing.
+ * The statistics of T take 64 bytes per point (n up to about 4 million at
+ * m = 256, l = 128); the persistent grid shrinks to the profile slots that
+ * fit in the rest (4 MB each at that m and l), so long series run on fewer
+ * compute units.  Results equal pst_mpdist_profile's.
+ * Every call on one GPU uses the same array: calls that overlap on one GPU
+ * (other threads, contexts or streams) race and must be serialised by the
+ * caller.  The call returns once its work is done.  PST_EINVAL as
+ * pst_mpdist_profile, and when n, m, l need more scratch than the array
+ * holds; PST_EDEVICE if the array's address could not be looked up. */
+int pst_mpdist_profile_noalloc(pst_ctx *ctx, const double *T_dev, int64_t n, const double *Q_dev, int32_t m,
+                               int32_t l, int32_t k, float *out_dev);
+
 /* eq. 15: the profile set D = (D_0 .. D_{nseg-1}), D_s = MPD(S_s, T).
  * D_dev: float32, row s at D_dev + s*ld, ld >= n-m+1.  dmax_dev (optional,
  * may be NULL): float32[1], receives max over all entries of D (the

@@ -62,6 +62,7 @@ def load():
         "pst_select_length_workspace_bytes": (c_size_t, [c_int64, POINTER(c_int32), c_int32,
                                                          POINTER(c_int32), c_int32]),
         "pst_mpdist_profile": (c_int, [P, P, c_int64, P, c_int32, c_int32, c_int32, P, P, c_size_t]),
+        "pst_mpdist_profile_noalloc": (c_int, [P, P, c_int64, P, c_int32, c_int32, c_int32, P]),
         "pst_profile_set": (c_int, [P, P, c_int64, c_int32, c_int32, c_int32, P, c_int64, P, P,
                                     c_size_t]),
         "pst_snippets": (c_int, [P, P, c_int64, c_int32, c_int32, c_int32, c_int32,

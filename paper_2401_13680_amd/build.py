@@ -14,7 +14,8 @@ LIB = os.path.join(HERE, "libpst.so")
 PROBE_LIB = os.path.join(HERE, "libpst_probe.so")
 # sha256 of the profile kernel's gfx950 instructions in the last build
 KERNEL_HASH = os.path.join(HERE, "libpst.k_profile.sha256")
-SOURCES = ["pst_stats.hip", "pst_profile.hip", "pst_greedy.hip", "pst_label.hip", "pst_api.cpp", "pst_sched.cpp"]
+SOURCES = ["pst_stats.hip", "pst_profile.hip", "pst_greedy.hip", "pst_label.hip", "pst_noalloc.hip", "pst_api.cpp",
+           "pst_sched.cpp"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

@@ -37,6 +37,7 @@ struct pst_ctx {
     bool timing;
     bool timed;
     hipEvent_t ev0, ev1;
+    void *fixed_scratch;          // device address of the fixed scratch on this device (or null)
     // options (pst_set_option)
     int opt_graph = 1, opt_autotune = 0, opt_grid = 0, opt_dynamic = 1, opt_batched = 1, opt_anchor = 0;
     std::vector<GraphEntry> graphs;
@@ -832,6 +833,15 @@ int pst_create(pst_ctx **out, int device, void *hip_stream) {
     c->ev0 = c->ev1 = nullptr;
     c->cap = nullptr;
     c->err[0] = 0;
+    // the device address of the fixed scratch of pst_mpdist_profile_noalloc,
+    // looked up once per device with that device current
+    c->fixed_scratch = nullptr;
+    int prev = -1;
+    if (hipGetDevice(&prev) == hipSuccess && hipSetDevice(device) == hipSuccess) {
+        if (static_scratch(device, &c->fixed_scratch) != hipSuccess) c->fixed_scratch = nullptr;
+        (void)hipSetDevice(prev);
+    }
+    (void)hipGetLastError();
     *out = c;
     return PST_OK;
 }
@@ -991,6 +1001,36 @@ int pst_mpdist_profile(pst_ctx *ctx, const double *T_dev, int64_t n, const doubl
     j.nq = 1;
     j.grid = profile_grid(L.ntile, L.w);
     HIPCHK(ctx, timed_profile(ctx, j));
+    return PST_OK;
+}
+
+int pst_mpdist_profile_noalloc(pst_ctx *ctx, const double *T_dev, int64_t n, const double *Q_dev, int32_t m,
+                               int32_t l, int32_t k, float *out_dev) {
+    int rc = begin(ctx);
+    if (rc) return rc;
+    Layout L;
+    if ((rc = plan(ctx, n, m, l, k, 0, &L, false))) return rc;
+    if (!T_dev || !Q_dev || !out_dev) return fail(ctx, PST_EINVAL, "null pointer argument");
+    if (!ctx->fixed_scratch) return fail(ctx, PST_EDEVICE, "the fixed device scratch is not available");
+    // the statistics of T and Q (at the head of the workspace layout), then
+    // profile scratch for as many persistent workgroups as fit (at least one)
+    const size_t cap = static_scratch_bytes();
+    const size_t used = al(L.o_Q + L.sQ.total);
+    const size_t slot = sizeof(float) * profile_scratch_floats(1, L.w);
+    if (used + slot > cap)
+        return fail(ctx, PST_EINVAL, "n=%lld, m=%d, l=%d needs %zu bytes of scratch, the fixed scratch holds %zu",
+                    (long long)n, m, l, used + slot, cap);
+    char *ws = (char *)ctx->fixed_scratch;
+    if ((rc = series_stats(ctx, T_dev, ws + L.o_T, L.sT, "T"))) return rc;
+    if ((rc = series_stats(ctx, Q_dev, ws + L.o_Q, L.sQ, "Q"))) return rc;
+    ProfileJob j = job_for(L, ws, out_dev, L.Nm, nullptr);
+    j.row = stats_view(ws + L.o_Q, L.sQ);
+    j.row_stride = 0;
+    j.nq = 1;
+    j.rw = (float *)(ws + used);
+    j.grid = (int32_t)std::min<int64_t>(profile_grid(L.ntile, L.w), (int64_t)((cap - used) / slot));
+    HIPCHK(ctx, timed_profile(ctx, j));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     return PST_OK;
 }
 

@@ -138,4 +138,9 @@ struct LabelJob {
 };
 hipError_t launch_label_f1(const LabelJob &job, hipStream_t st);
 
+// The fixed device scratch of the allocation-free entry point: its size, and
+// its device address on `device` (which must be current), looked up once.
+size_t static_scratch_bytes();
+hipError_t static_scratch(int device, void **ptr);
+
 }  // namespace pst
