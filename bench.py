@@ -43,7 +43,12 @@ TRAFFIC_NOTE = os.path.join(ROOT, "profiles", "k_profile_traffic.md")
 KERNEL_HASH = os.path.join(ROOT, "paper_2401_13680_amd", "libpst.k_profile.sha256")
 
 
-def measured_traffic(cells_per_launch):
+def progress(msg):
+    """A progress line on stderr (the JSON result stays the last line of stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def measured_traffic(cells_per_launch, field="hbm bytes per cell"):
     """HBM bytes per profile launch: the committed FETCH_SIZE + WRITE_SIZE
     measurement (bytes per distance-matrix cell, copy-calibrated) times the
     launch's cells, or None once the profile kernel's machine code differs from
@@ -58,9 +63,9 @@ def measured_traffic(cells_per_launch):
         if ":" in line and line.startswith("- "):
             key, _, val = line[2:].partition(":")
             fields[key.strip()] = val.strip().strip("`")
-    if fields.get("k_profile code sha256") != built or "hbm bytes per cell" not in fields:
+    if fields.get("k_profile code sha256") != built or field not in fields:
         return None
-    return float(fields["hbm bytes per cell"]) * cells_per_launch
+    return float(fields[field]) * cells_per_launch
 
 
 def cpu_baseline(x, m, l, k, nseg_sample=20):
@@ -107,8 +112,11 @@ def probe_bench(args):
     L = _lib.load()
     L.pst_probe_read.argtypes = [ctypes.POINTER(ctypes.c_ulonglong), ctypes.c_int]
     buf = (ctypes.c_ulonglong * 32)()
-    n, m, l, K = WORKLOAD["n"], WORKLOAD["m"], WORKLOAD["l"], WORKLOAD["K"]
+    m = args.probe_m or WORKLOAD["m"]
+    l = m // 2
     T = torch.from_numpy(synth.workload_series(WORKLOAD["name"])).cuda()
+    if args.probe_geometry:
+        api.set_geometry(m - l + 1, int(args.probe_geometry, 0))
     api.profile_set(T, m, l)
     torch.cuda.synchronize()
     L.pst_probe_read(buf, 1)
@@ -116,7 +124,7 @@ def probe_bench(args):
     torch.cuda.synchronize()
     L.pst_probe_read(buf, 1)
     tot = buf[16] + buf[21]
-    out = dict(workload=WORKLOAD["name"], counts={v: int(buf[k]) for k, v in PROBE_NAMES.items()},
+    out = dict(workload=WORKLOAD["name"], m=m, l=l, geometry=hex(api.geometry(m - l + 1)), counts={v: int(buf[k]) for k, v in PROBE_NAMES.items()},
                wave_cycles={v.strip(): int(buf[k]) for k, v in PROBE_PHASES.items()},
                share_of_wave_time={v.strip(): round(buf[k] / tot, 4) for k, v in PROBE_PHASES.items()})
     print(json.dumps(out), flush=True)
@@ -135,7 +143,12 @@ def sweep_bench(args):
     T = torch.from_numpy(x).cuda()
     cells = sum((n // m) * (m - m // 2 + 1) * (n - m // 2 + 1) for m in ms)
     res = {}
-    for mode, kw in (("batched_graph", dict(batched=True, graph=True)), ("plain", dict(batched=False))):
+    modes = [("batched_graph", dict(batched=True, graph=True)), ("plain", dict(batched=False)),
+             ("batched_graph_one_launch", dict(batched=True, graph=True, one_launch=True))]
+    if not args.no_tune:
+        modes.append(("batched_graph_tuned", dict(batched=True, graph=True, tune_geometry=True)))
+    for mode, kw in modes:
+        progress(f"sweep mode {mode}")
         for _ in range(args.warmup):
             api.select_length(T, ms, K, **kw)
         torch.cuda.synchronize()
@@ -161,6 +174,16 @@ def sweep_bench(args):
                            step="all 15 lengths: stats + profiles in one launch + greedy + criterion, one HIP graph"),
                plain_one_length_at_a_time=dict(value=cells / res["plain"][0], ms_per_step=res["plain"][0] * 1e3),
                batched_over_plain=res["plain"][0] / dt,
+               one_launch_all_lengths=dict(value=cells / res["batched_graph_one_launch"][0],
+                                           ms_per_step=res["batched_graph_one_launch"][0] * 1e3,
+                                           m_best=res["batched_graph_one_launch"][1],
+                                           per_shape_over_one_launch=res["batched_graph_one_launch"][0] / dt),
+               tuned_geometries=(dict(value=cells / res["batched_graph_tuned"][0],
+                                      ms_per_step=res["batched_graph_tuned"][0] * 1e3,
+                                      m_best=res["batched_graph_tuned"][1],
+                                      over_builtin=dt / res["batched_graph_tuned"][0],
+                                      geometry={str(m): hex(api.geometry(m - m // 2 + 1)) for m in ms})
+                                 if "batched_graph_tuned" in res else None),
                labelling=dict(m_best=r["m_best"], classes=C, macro_f1=lab["macro_f1"],
                               f1=[round(v, 4) for v in lab["f1"]]))
     print(json.dumps(out), flush=True)
@@ -206,7 +229,11 @@ def multi_bench(args):
                config=dict(workload="multi4_n100000", n=n, d=d, m=m, l=l, K=K, cells_per_step=cells,
                            step="stats of every coordinate + all profiles in one launch + greedy + neighbours"),
                plain_one_coordinate_at_a_time=dict(value=cells / res["plain"][0], ms_per_step=res["plain"][0] * 1e3),
-               batched_over_plain=res["plain"][0] / dt, batched_equals_plain=same,
+               batched_over_plain=res["plain"][0] / dt,
+               one_launch_all_lengths=dict(value=cells / res["batched_graph_one_launch"][0],
+                                           ms_per_step=res["batched_graph_one_launch"][0] * 1e3,
+                                           m_best=res["batched_graph_one_launch"][1],
+                                           per_shape_over_one_launch=res["batched_graph_one_launch"][0] / dt), batched_equals_plain=same,
                labelling=dict(classes=C, macro_f1_per_coordinate=[round(v, 4) for v in f1]))
     print(json.dumps(out), flush=True)
 
@@ -351,7 +378,8 @@ def cpu_baseline_serving(reqs, per_m=4, n_max=150_000):
             t0 = time.perf_counter()
             pool.map(_cpu_task, tasks, chunksize=1)
             wall = time.perf_counter() - t0
-        one = [_cpu_task(t) for t in tasks[:3]]
+        firsts = [next(i for i, t in enumerate(tasks) if t[1] == m) for m in sorted({t[1] for t in tasks})]
+        one = [_cpu_task(tasks[i]) for i in firsts]
     finally:
         for k, v in old.items():
             if v is None:
@@ -366,8 +394,8 @@ def cpu_baseline_serving(reqs, per_m=4, n_max=150_000):
                 sample=f"profile of the middle segment of {len(tasks)} requests of the stream ({per_m} per m, "
                        f"n <= {n_max}; {sum(cells):.3g} cells, {wall:.1f} s) on a process pool, numpy FP64, "
                        f"BLAS 1 thread per process",
-                one_core=dict(value=sum(cells[:3]) / sum(one), unit="cells/s",
-                              sample=f"3 of those segments, {sum(one):.1f} s"),
+                one_core=dict(value=sum(cells[i] for i in firsts) / sum(one), unit="cells/s",
+                              sample=f"one of those segments per m ({len(firsts)}), {sum(one):.1f} s"),
                 host=dict(nproc=os.cpu_count(), affinity=cores, cpu=model))
 
 
@@ -391,12 +419,40 @@ def serve_bench(args):
     Tw = [torch.from_numpy(r.x).cuda() for r in warm]
     torch.cuda.synchronize()
     budget, slots = 160 << 30, 32
-    if args.plain_only:  # the plain pass alone (for hardware-counter runs of its profile launches)
-        for T, r in zip(Ts, reqs):
-            api.snippets(T, r.m, r.l, r.K)
+    # tile geometry of each m of the stream, tuned on a series of the same
+    # generator that is not part of the stream (both paths below use it)
+    geometry = {}
+    progress(f"{nreq} requests, {cells:.3g} cells; tuning tile geometries")
+    if not args.no_tune:
+        for m in sorted({r.m for r in reqs}):
+            xt = synth.regime_series(200_000, 900 + m, synth.SHAPES5).x
+            code, _ = api.tune_geometry(torch.from_numpy(xt).cuda(), m, m // 2)
+            geometry[str(m)] = api.decode_geometry(code)
+    if args.plain_only:  # the plain pass alone (for profiler runs of its profile launches)
+        progress("plain pass")
+        ctx = api.context(0)
+        for T, r in zip(Tw[:3], warm[:3]):
+            api.snippets(T, r.m, r.l, r.K, ctx=ctx)
         torch.cuda.synchronize()
+        ctx.L.pst_set_timing(ctx.h, 1)
+        kms, ms = [], ctypes.c_float()
+        for T, r in zip(Ts, reqs):
+            api.snippets(T, r.m, r.l, r.K, ctx=ctx)
+            ctx.check(ctx.L.pst_last_profile_ms(ctx.h, ctypes.byref(ms)))
+            kms.append(ms.value)
+        torch.cuda.synchronize()
+        ctx.L.pst_set_timing(ctx.h, 0)
+        if args.calibrate_copy:  # one 1 GiB device copy: the counters' reading for known bytes
+            a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+            b = torch.empty_like(a)
+            torch.cuda.synchronize()
+            b.copy_(a)
+            torch.cuda.synchronize()
         print(json.dumps(dict(workload=f"poisson20_serving_{nreq}", plain_only=True, cells=cells,
-                              profile_launches=nreq)), flush=True)
+                              profile_launches=nreq, kernel_ms=float(np.mean(kms)),
+                              launch_m=[r.m for r in reqs], launch_cells=[cells_of(r) for r in reqs],
+                              tile_geometry_by_m={m: hex(api.geometry(m - m // 2 + 1))
+                                                  for m in sorted({r.m for r in reqs})})), flush=True)
         return
 
     def serve_all(srv, series, rs):
@@ -404,6 +460,7 @@ def serve_bench(args):
         srv.drain()
         return [srv.poll(t) for t in tk]
 
+    progress("served pass")
     srv = api.Server(0, hbm_budget_bytes=budget, max_slots=slots)
     if warm:
         serve_all(srv, Tw, warm)
@@ -417,6 +474,7 @@ def serve_bench(args):
 
     # plain: pst_snippets one request after another, the profile kernel timed
     # by the library's events around each launch
+    progress("plain pass")
     ctx = api.context(0)
     L = ctx.L
     for T, r in zip(Tw[:3], warm[:3]):
@@ -436,6 +494,7 @@ def serve_bench(args):
     same = all(a["records"] == b for a, b in zip(served, plain_recs))
 
     # latency: the stream replayed at its own arrival times
+    progress("Poisson replay")
     t0 = time.perf_counter()
     tickets = []
     for T, r in zip(Ts, reqs):
@@ -449,6 +508,7 @@ def serve_bench(args):
     srv.close()
 
     # the same stream submitted from host memory (PCIe copies included)
+    progress("host-memory submissions")
     srv = api.Server(0, hbm_budget_bytes=budget, max_slots=slots)
     t0 = time.perf_counter()
     serve_all(srv, [r.x for r in reqs], reqs)
@@ -459,6 +519,14 @@ def serve_bench(args):
     achieved = OPS_PER_CELL * cells / (k_ms * 1e-3) / 1e12
     peak = PEAK_LANE_OPS / 1e12
     offered = cells / reqs[-1].arrival_s
+    per_m = {}
+    for r, t in zip(reqs, kms):
+        a = per_m.setdefault(r.m, [0.0, 0.0, 0])
+        a[0] += cells_of(r)
+        a[1] += t
+        a[2] += 1
+    kernel_by_m = {str(m): dict(requests=a[2], cells_per_s=a[0] / (a[1] * 1e-3), geometry=hex(api.geometry(m - m // 2 + 1)))
+                   for m, a in sorted(per_m.items())}
     out = dict(metric="MPdist distance-matrix cells/sec on 1 MI355X; p50/p99 request latency",
                value=cells / sat, unit="cells/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
                ms_per_step=sat * 1e3 / args.steps, higher_is_better=True, scaling="weak", vs_baseline=None,
@@ -480,8 +548,10 @@ def serve_bench(args):
                              kernel="k_profile", kernel_ms=k_ms / nreq, launches=nreq,
                              ops_per_cell=OPS_PER_CELL,
                              note="profile launches of the plain pass over the same requests, "
-                                  "HIP events around each launch"))
+                                  "HIP events around each launch"),
+               profile_kernel_by_m=kernel_by_m, tile_geometry_by_m=geometry or "built-in")
     if not args.no_cpu_baseline:
+        progress("CPU baseline")
         out["cpu_baseline"] = cpu_baseline_serving(reqs)
     print(json.dumps(out), flush=True)
 
@@ -535,6 +605,9 @@ def main():
     ap.add_argument("--workload", default="serve",
                     choices=["serve", "plain", "serve_order", "sweep", "multi", "schedule", "blocked", "probe"])
     ap.add_argument("--requests", type=int, default=40, help="serve_order: number of requests")
+    ap.add_argument("--probe-m", type=int, default=0, help="probe: snippet length (l = m/2)")
+    ap.add_argument("--probe-geometry", default="", help="probe: tile geometry code to install first")
+    ap.add_argument("--no-tune", action="store_true", help="serve, sweep: keep the built-in tile geometries")
     ap.add_argument("--plain-only", action="store_true",
                     help="serve: only the plain per-request pass (one profile launch per request)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -606,7 +679,7 @@ def main():
                     step="stats + all segment profiles + greedy + neighbours"),
         latency_ms=dict(p50=float(np.percentile(lat, 50)), p99=float(np.percentile(lat, 99))),
         roofline=dict(bound="alu", achieved=achieved, peak=peak, unit="Tops/s (VALU lane-ops)",
-                      frac=achieved / peak, traffic=measured_traffic(cells), kernel="k_profile",
+                      frac=achieved / peak, traffic=measured_traffic(cells, "hbm bytes per cell at m=256"), kernel="k_profile",
                       kernel_ms=k_ms, ops_per_cell=OPS_PER_CELL),
     )
     if args.calibrate_copy:

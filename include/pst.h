@@ -372,6 +372,14 @@ int pst_label_f1(pst_ctx *ctx, const int32_t *owner_dev, int64_t n, int32_t m, i
  *   PST_OPT_SWEEP_BATCHED  one launch for all candidates [1]; 0 runs the
  *                          candidates one after another (the plain path)
  * None of the above changes any result.
+ *   PST_OPT_TUNE_GEOMETRY  before a batched sweep, choose each length's tile
+ *                          geometry by timing every candidate (pst_tune_geometry)
+ *                          [0, 1]; results stay within the profile tolerance
+ *                          of the built-in geometry, not bit for bit
+ *   PST_OPT_SWEEP_ONE_LAUNCH  run every length of a batched sweep in one
+ *                          launch with the widest length's tile geometry [0, 1]
+ *                          (0: one launch per workgroup shape among the
+ *                          lengths); results within the profile tolerance
  *   PST_OPT_ANCHOR_EVERY   R > 0: besides the FP64 anchor at the first cell of
  *                          each diagonal of a sub-tile (at most w-1 FP32 steps
  *                          apart), re-anchor every diagonal with an exact FP64
@@ -384,9 +392,36 @@ enum {
     PST_OPT_PROFILE_GRID = 3,
     PST_OPT_DYNAMIC_TILES = 4,
     PST_OPT_SWEEP_BATCHED = 5,
-    PST_OPT_ANCHOR_EVERY = 6
+    PST_OPT_ANCHOR_EVERY = 6,
+    PST_OPT_TUNE_GEOMETRY = 7,
+    PST_OPT_SWEEP_ONE_LAUNCH = 8
 };
 int pst_set_option(pst_ctx *ctx, int option, int64_t value);
+
+/* Tile geometry of the profile kernel (the parallel decomposition of eqs.
+ * 9-13 on the GPU: workgroup size, diagonals per thread, rows per chunk,
+ * selection threads, sub-tile width), per w = m-l+1, as one code: threads/256
+ * << 24 | diagonals << 16 | rows << 8 | selection threads/256 << 4 |
+ * sub-tile windows/992.  The choice is process-wide and applies to every
+ * entry point; every workspace size already covers any candidate.  Geometries agree
+ * within the profile tolerance, not bit for bit (each sub-tile anchors its
+ * diagonals afresh), so change one only between calls, not while others run.
+ * pst_geometry_candidates writes up to max codes the kernels can run for w and
+ * returns how many there are; pst_geometry returns the code in use;
+ * pst_set_geometry installs a candidate (0 restores the built-in choice;
+ * PST_EINVAL for a code that is not a candidate).  pst_tune_geometry times
+ * every candidate on the same segments of T (as many as give about sixteen
+ * tiles per resident workgroup; best of three launches; workspace as
+ * pst_workspace_bytes(n, m, l, 1)),
+ * installs the fastest and returns its code and launch time; the choice is
+ * remembered per (GPU architecture, w) in the process and, if
+ * PST_AUTOTUNE_CACHE names a file, there ("geo arch w code ms" lines), and
+ * reused without timing. */
+int pst_geometry_candidates(int32_t w, int32_t *codes, int32_t max);
+int32_t pst_geometry(int32_t w);
+int pst_set_geometry(int32_t w, int32_t code);
+int pst_tune_geometry(pst_ctx *ctx, const double *T_dev, int64_t n, int32_t m, int32_t l, int32_t *code_out,
+                      float *ms_out, void *ws_dev, size_t ws_bytes);
 
 /* Instrumentation.  With timing on, the profile kernel launched by each call
  * (eqs. 9-13, the dominant cost) is bracketed by two HIP events recorded on the

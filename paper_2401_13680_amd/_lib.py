@@ -19,7 +19,8 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "pst.h")
 
 PST_OK, PST_EINVAL, PST_ENOMEM, PST_EDEVICE, PST_ENOTREADY, PST_ECANCELED = 0, -1, -2, -3, -4, -5
 PST_OPT_SWEEP_GRAPH, PST_OPT_AUTOTUNE, PST_OPT_PROFILE_GRID, PST_OPT_DYNAMIC_TILES, \
-    PST_OPT_SWEEP_BATCHED, PST_OPT_ANCHOR_EVERY = 1, 2, 3, 4, 5, 6
+    PST_OPT_SWEEP_BATCHED, PST_OPT_ANCHOR_EVERY, PST_OPT_TUNE_GEOMETRY, PST_OPT_SWEEP_ONE_LAUNCH = \
+    1, 2, 3, 4, 5, 6, 7, 8
 STATUS_NAMES = {0: "PST_OK", -1: "PST_EINVAL", -2: "PST_ENOMEM", -3: "PST_EDEVICE",
                 -4: "PST_ENOTREADY", -5: "PST_ECANCELED"}
 
@@ -95,6 +96,11 @@ def load():
                                           POINTER(c_int32), POINTER(c_double)]),
         "pst_set_timing": (c_int, [P, c_int]),
         "pst_set_option": (c_int, [P, c_int, c_int64]),
+        "pst_geometry_candidates": (c_int, [c_int32, POINTER(c_int32), c_int32]),
+        "pst_geometry": (c_int32, [c_int32]),
+        "pst_set_geometry": (c_int, [c_int32, c_int32]),
+        "pst_tune_geometry": (c_int, [P, P, c_int64, c_int32, c_int32, POINTER(c_int32), POINTER(c_float), P,
+                                      c_size_t]),
         "pst_server_create": (c_int, [POINTER(P), c_int, c_size_t, c_int32]),
         "pst_server_destroy": (None, [P]),
         "pst_server_last_error": (c_char_p, [P]),

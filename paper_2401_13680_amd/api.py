@@ -185,16 +185,20 @@ def snippets_multi(X, m: int, l: int, K: int, k: int = 0, owner: bool = False, c
 
 def select_length(T, m_list, K: int, l_list=None, profiles: bool = False, owner: bool = False,
                   batched: bool = True, graph: bool = True, autotune: bool = False,
-                  ctx: Context | None = None):
+                  tune_geometry: bool = False, one_launch: bool = False, ctx: Context | None = None):
     """eq. 18: the best snippet length among m_list and its snippets.
 
     batched: all candidates in one persistent launch (else one after another);
-    graph: capture the batched sweep as a HIP graph; autotune: tune its launch."""
+    graph: capture the batched sweep as a HIP graph; autotune: tune its launch;
+    tune_geometry: choose every length's tile geometry by timing first;
+    one_launch: every length in one launch (else one per workgroup shape)."""
     T = _series(T)
     ctx = ctx or context(T.device.index)
     ctx.check(ctx.L.pst_set_option(ctx.h, _lib.PST_OPT_SWEEP_BATCHED, int(batched)))
     ctx.check(ctx.L.pst_set_option(ctx.h, _lib.PST_OPT_SWEEP_GRAPH, int(graph)))
     ctx.check(ctx.L.pst_set_option(ctx.h, _lib.PST_OPT_AUTOTUNE, int(autotune)))
+    ctx.check(ctx.L.pst_set_option(ctx.h, _lib.PST_OPT_TUNE_GEOMETRY, int(tune_geometry)))
+    ctx.check(ctx.L.pst_set_option(ctx.h, _lib.PST_OPT_SWEEP_ONE_LAUNCH, int(one_launch)))
     n = T.numel()
     num = len(m_list)
     ms = (c_int32 * num)(*m_list)
@@ -476,3 +480,44 @@ def partition_lengths(model: RuntimeModel, n: int, m_list, parts: int, l_list=No
     if rc != 0:
         raise PstError(rc, "pst_partition_lengths failed")
     return list(po), list(lo)
+
+
+# ---------------------------------------------------------------- tile geometry
+def decode_geometry(code: int) -> dict:
+    """The profile kernel's tile geometry from its code (include/pst.h)."""
+    return dict(threads=((code >> 24) & 0xF) * 256, diagonals_per_thread=(code >> 16) & 0xFF,
+                rows_per_chunk=(code >> 8) & 0xFF, selection_threads=((code >> 4) & 0xF) * 256,
+                subtile_windows=(code & 0xF) * 992)
+
+
+def geometry_candidates(w: int) -> list:
+    L = _lib.load()
+    n = L.pst_geometry_candidates(w, None, 0)
+    buf = (c_int32 * max(n, 1))()
+    L.pst_geometry_candidates(w, buf, n)
+    return list(buf)[:n]
+
+
+def geometry(w: int) -> int:
+    return int(_lib.load().pst_geometry(w))
+
+
+def set_geometry(w: int, code: int):
+    rc = _lib.load().pst_set_geometry(w, code)
+    if rc != 0:
+        raise PstError(rc, f"geometry {code:#x} is not a candidate for w={w}")
+
+
+def tune_geometry(T, m: int, l: int, ctx: Context | None = None):
+    """Time every tile geometry for w = m-l+1 on T's segment profiles and
+    install the fastest (process-wide); returns (code, ms)."""
+    T = _series(T)
+    ctx = ctx or context(T.device.index)
+    n = T.numel()
+    nb = ctx.L.pst_workspace_bytes(n, m, l, 1)
+    if nb == 0:
+        raise PstError(-1, f"invalid sizes n={n} m={m} l={l}")
+    ws = ctx.workspace(nb)
+    code, ms = c_int32(), c_float()
+    ctx.check(ctx.L.pst_tune_geometry(ctx.h, _ptr(T), n, m, l, byref(code), byref(ms), _ptr(ws), ws.numel()))
+    return code.value, ms.value

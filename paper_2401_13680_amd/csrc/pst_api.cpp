@@ -40,6 +40,7 @@ struct pst_ctx {
     void *fixed_scratch;          // device address of the fixed scratch on this device (or null)
     // options (pst_set_option)
     int opt_graph = 1, opt_autotune = 0, opt_grid = 0, opt_dynamic = 1, opt_batched = 1, opt_anchor = 0;
+    int opt_tune_geometry = 0, opt_one_launch = 0;
     std::vector<GraphEntry> graphs;
     char err[512];
 };
@@ -109,7 +110,7 @@ int plan(pst_ctx *c, int64_t n, int32_t m, int32_t l, int32_t k, int32_t K, Layo
     size_t o = 0;
     L->o_T = o;      o = al(o + L->sT.total);
     L->o_Q = o;      o = al(o + L->sQ.total);
-    L->o_rw = o;     o = al(o + (with_rw ? sizeof(float) * profile_scratch_floats(L->grid, w) : 0));
+    L->o_rw = o;     o = al(o + (with_rw ? sizeof(float) * profile_scratch_bound(L->Nm, nseg, w) : 0));
     L->o_D = o;      o = al(o + sizeof(float) * (size_t)nseg * L->Nm);
     L->o_M = o;      o = al(o + sizeof(float) * L->Nm);
     L->o_part = o;   o = al(o + sizeof(double) * (size_t)nseg * L->nblk);
@@ -280,7 +281,7 @@ int plan_multi(pst_ctx *c, int32_t d, int64_t n, int32_t m, int32_t l, int32_t k
     P->d = d;
     P->grid = profile_grid(P->L.ntile * P->L.nseg * d, P->L.w);
     size_t o = (size_t)d * P->L.total;
-    P->o_rw = o;       o = al(o + sizeof(float) * profile_scratch_floats(P->grid, P->L.w));
+    P->o_rw = o;       o = al(o + sizeof(float) * profile_scratch_bound(P->L.Nm, (int64_t)P->L.nseg * d, P->L.w));
     P->o_counter = o;  o = al(o + 256);
     P->total = o;
     return PST_OK;
@@ -368,7 +369,7 @@ int plan_blocked(pst_ctx *c, int64_t n, int32_t m, int32_t l, int32_t k, int32_t
     P->o_iota = o;   o = al(o + sizeof(int32_t) * K);
     P->o_dmax = o;   o = al(o + 256);
     P->o_crit = o;   o = al(o + sizeof(double) * (L.nblk2 + 1));
-    P->o_rw = o;     o = al(o + sizeof(float) * profile_scratch_floats(P->grid, L.w));
+    P->o_rw = o;     o = al(o + sizeof(float) * profile_scratch_bound(L.Nm, B, L.w));
     P->total = o;
     return PST_OK;
 }
@@ -516,6 +517,22 @@ struct SweepPlan {
 };
 
 
+// Lengths of each workgroup shape run in a launch of that shape: the widest
+// w of every shape among the lengths, widest first (redone when a tuned
+// geometry changes the shapes).
+void sweep_shapes(SweepPlan *P) {
+    P->grid = profile_slots(P->wmax);
+    P->shape_w.clear();
+    std::vector<int32_t> ws_sorted;
+    for (const Layout &L : P->L) ws_sorted.push_back(L.w);
+    std::sort(ws_sorted.begin(), ws_sorted.end(), std::greater<int32_t>());
+    for (int32_t w : ws_sorted) {
+        bool seen = false;
+        for (int32_t v : P->shape_w) seen |= profile_shape(v) == profile_shape(w);
+        if (!seen) P->shape_w.push_back(w);
+    }
+}
+
 int plan_sweep(pst_ctx *c, int64_t n, const int32_t *m_list, int32_t nm, const int32_t *l_list,
                int32_t K, SweepPlan *P) {
     if (!m_list || nm < 1) return fail(c, PST_EINVAL, "empty candidate list");
@@ -542,20 +559,11 @@ int plan_sweep(pst_ctx *c, int64_t n, const int32_t *m_list, int32_t nm, const i
         P->o_stats.push_back(o);
         o = al(o + P->SL.back().total);
     }
-    P->grid = profile_slots(P->wmax);
-    // lengths of each workgroup shape run in a launch of that shape
-    std::vector<int32_t> ws_sorted;
-    for (int i = 0; i < nm; ++i) ws_sorted.push_back(P->L[i].w);
-    std::sort(ws_sorted.begin(), ws_sorted.end(), std::greater<int32_t>());
+    sweep_shapes(P);
+    // scratch for any geometry of any length (one may be tuned after planning)
     size_t scratch = 0;
-    for (int32_t w : ws_sorted) {
-        bool seen = false;
-        for (int32_t v : P->shape_w) seen |= profile_shape(v) == profile_shape(w);
-        if (!seen) {
-            P->shape_w.push_back(w);
-            scratch = std::max(scratch, profile_scratch_floats(profile_slots(w), w));
-        }
-    }
+    for (int i = 0; i < nm; ++i)
+        scratch = std::max(scratch, profile_scratch_bound(P->L[i].Nm, (int64_t)1 << 40, P->L[i].w));
     P->o_rw = o;
     o = al(o + sizeof(float) * scratch);
     P->o_counter = o;
@@ -636,11 +644,15 @@ int sweep_jobs(const SweepPlan &P, char *ws, int32_t grid, ProfileJob *jobs, int
 // shape among the lengths, widest first, each grid scaled like the widest
 // shape's (grid of P.grid).
 hipError_t launch_sweep_profiles(const SweepPlan &P, char *ws, int32_t grid, bool dynamic, hipStream_t st,
-                                 int32_t anchor) {
+                                 int32_t anchor, bool one_launch = false) {
     ProfileJob jobs[kMaxJobs];
     const int nj = sweep_jobs(P, ws, grid, jobs, anchor);
     uint32_t *counter = (uint32_t *)(ws + P.o_counter);
     hipError_t e;
+    if (one_launch) {  // every length in the widest one's geometry
+        if ((e = launch_fill_u32(counter, 1, 0u, st)) != hipSuccess) return e;
+        return launch_profile_batch(jobs, nj, grid, dynamic ? counter : nullptr, st);
+    }
     int done = 0;
     for (int32_t wg : P.shape_w) {
         const int32_t shape = profile_shape(wg);
@@ -658,13 +670,13 @@ hipError_t launch_sweep_profiles(const SweepPlan &P, char *ws, int32_t grid, boo
 }
 
 hipError_t enqueue_sweep(const SweepPlan &P, const double *T, char *ws, int32_t grid, bool dynamic,
-                         hipStream_t st, int32_t anchor) {
+                         hipStream_t st, int32_t anchor, bool one_launch) {
     hipError_t e;
     for (size_t j = 0; j < P.ls.size(); ++j)
         if ((e = launch_series_stats(T, ws + P.o_stats[j], P.SL[j], st)) != hipSuccess) return e;
     for (int i = 0; i < P.nm; ++i)
         if ((e = launch_fill_u32((uint32_t *)(ws + P.gb[i].dmax), 1, 0u, st)) != hipSuccess) return e;
-    if ((e = launch_sweep_profiles(P, ws, grid, dynamic, st, anchor)) != hipSuccess) return e;
+    if ((e = launch_sweep_profiles(P, ws, grid, dynamic, st, anchor, one_launch)) != hipSuccess) return e;
     SweepGather Gt{};
     Gt.nm = P.nm;
     Gt.K = P.K;
@@ -698,6 +710,9 @@ std::mutex g_tune_mu;
 std::map<TuneKey, TuneVal> g_tuned;
 bool g_tune_loaded = false;
 
+// Tile geometries chosen per (arch, w), from timing or the cache file.
+std::map<std::pair<std::string, int>, std::pair<int32_t, float>> g_geo_tuned;
+
 void tune_load_locked() {
     if (g_tune_loaded) return;
     g_tune_loaded = true;
@@ -705,12 +720,100 @@ void tune_load_locked() {
     if (!path) return;
     FILE *f = std::fopen(path, "r");
     if (!f) return;
-    char arch[64];
-    int wm, tl, gr, dy;
-    float ms;
-    while (std::fscanf(f, "%63s %d %d %d %d %f", arch, &wm, &tl, &gr, &dy, &ms) == 6)
-        g_tuned[TuneKey(arch, wm, tl)] = TuneVal{gr, dy, ms};
+    char line[256];
+    while (std::fgets(line, sizeof line, f)) {
+        char arch[64];
+        int wm, tl, gr, dy, code;
+        float ms;
+        if (std::sscanf(line, "geo %63s %d %d %f", arch, &wm, &code, &ms) == 4)
+            g_geo_tuned[{arch, wm}] = {code, ms};
+        else if (std::sscanf(line, "%63s %d %d %d %d %f", arch, &wm, &tl, &gr, &dy, &ms) == 6)
+            g_tuned[TuneKey(arch, wm, tl)] = TuneVal{gr, dy, ms};
+    }
     std::fclose(f);
+}
+
+std::string device_arch(pst_ctx *c) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, c->device) != hipSuccess) return "unknown";
+    return std::string(prop.gcnArchName).substr(0, 6);
+}
+
+// The tile geometry of one profile job's w: every candidate the kernels can
+// run is timed on the same queries of the job (as many as give about sixteen
+// tiles per resident workgroup of the geometry in use: long enough to measure,
+// short enough to repeat; best of three launches after a warm-up), the
+// fastest is installed for that w process-wide and
+// appended to the cache file; a w seen before (in this process or the file)
+// takes the remembered choice without timing.  The job's statistics must be
+// in place; its D rows are overwritten.
+int tune_geometry_job(pst_ctx *c, ProfileJob J, int32_t *code_out, float *ms_out) {
+    const std::string arch = device_arch(c);
+    const int32_t w = J.w;
+    {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        tune_load_locked();
+        auto it = g_geo_tuned.find({arch, w});
+        if (it != g_geo_tuned.end() && profile_set_geometry(w, it->second.first)) {
+            *code_out = it->second.first;
+            *ms_out = it->second.second;
+            return PST_OK;
+        }
+    }
+    int32_t codes[64];
+    const int nc = std::min<int>(profile_geometry_candidates(w, codes, 64), 64);
+    hipEvent_t a, b;
+    HIPCHK(c, hipEventCreate(&a));
+    HIPCHK(c, hipEventCreate(&b));
+    int32_t best = profile_geometry(w);
+    float best_ms = 1e30f;
+    // the same queries for every candidate: enough for about sixteen tiles
+    // per resident workgroup of the geometry in use
+    const int64_t tq0 = (J.Nm + profile_tile_windows(w) - 1) / profile_tile_windows(w);
+    const int32_t nq = (int32_t)std::max<int64_t>(
+        1, std::min<int64_t>(J.nq, (16 * (int64_t)profile_slots(w) + tq0 - 1) / tq0));
+    for (int i = 0; i < nc; ++i) {
+        if (!profile_set_geometry(w, codes[i])) continue;
+        ProfileJob j = J;
+        const int64_t tiles_per_q = (j.Nm + profile_tile_windows(w) - 1) / profile_tile_windows(w);
+        j.nq = nq;
+        j.grid = profile_grid(tiles_per_q * j.nq, w);
+        float ms = 1e30f;
+        hipError_t e = profile_prepare(w);
+        for (int rep = 0; rep < 4 && e == hipSuccess; ++rep) {  // a warm-up, then the best of three
+            if ((e = hipEventRecord(a, c->stream)) != hipSuccess) break;
+            if ((e = launch_profile_batch(&j, 1, j.grid, nullptr, c->stream)) != hipSuccess) break;
+            if ((e = hipEventRecord(b, c->stream)) != hipSuccess) break;
+            if ((e = hipEventSynchronize(b)) != hipSuccess) break;
+            float t = 0.0f;
+            if ((e = hipEventElapsedTime(&t, a, b)) != hipSuccess) break;
+            if (rep > 0) ms = std::min(ms, t);
+        }
+        if (e != hipSuccess) {
+            (void)profile_set_geometry(w, 0);
+            (void)hipEventDestroy(a);
+            (void)hipEventDestroy(b);
+            return fail(c, PST_EDEVICE, "geometry tuning launch failed: %s", hipGetErrorString(e));
+        }
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = codes[i];
+        }
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    (void)profile_set_geometry(w, best);
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    g_geo_tuned[{arch, w}] = {best, best_ms};
+    if (const char *path = std::getenv("PST_AUTOTUNE_CACHE")) {
+        if (FILE *f = std::fopen(path, "a")) {
+            std::fprintf(f, "geo %s %d %d %.4f\n", arch.c_str(), w, best, best_ms);
+            std::fclose(f);
+        }
+    }
+    *code_out = best;
+    *ms_out = best_ms;
+    return PST_OK;
 }
 
 int64_t sweep_tiles(const SweepPlan &P) {
@@ -780,13 +883,15 @@ int run_sweep(pst_ctx *c, const SweepPlan &P, const double *T, char *ws, size_t 
     }
     for (int32_t wg : P.shape_w) HIPCHK(c, profile_prepare(wg));
     if (!c->opt_graph) {
-        HIPCHK(c, enqueue_sweep(P, T, ws, cfg.grid, cfg.dynamic != 0, c->stream, c->opt_anchor));
+        HIPCHK(c, enqueue_sweep(P, T, ws, cfg.grid, cfg.dynamic != 0, c->stream, c->opt_anchor, c->opt_one_launch));
     } else {
         std::vector<int64_t> key = {(int64_t)(uintptr_t)T, P.L[0].n, (int64_t)(uintptr_t)ws,
-                                    (int64_t)ws_bytes, P.nm, P.K, cfg.grid, cfg.dynamic, c->opt_anchor};
+                                    (int64_t)ws_bytes, P.nm, P.K, cfg.grid, cfg.dynamic, c->opt_anchor,
+                                    c->opt_one_launch};
         for (int i = 0; i < P.nm; ++i) {
             key.push_back(m_list[i]);
             key.push_back(l_list ? l_list[i] : m_list[i] / 2);
+            key.push_back(profile_geometry(P.L[i].w));
         }
         hipGraphExec_t exec = nullptr;
         for (const GraphEntry &g : c->graphs)
@@ -794,7 +899,8 @@ int run_sweep(pst_ctx *c, const SweepPlan &P, const double *T, char *ws, size_t 
         if (!exec) {
             if (!c->cap) HIPCHK(c, hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
             HIPCHK(c, hipStreamBeginCapture(c->cap, hipStreamCaptureModeRelaxed));
-            const hipError_t eq = enqueue_sweep(P, T, ws, cfg.grid, cfg.dynamic != 0, c->cap, c->opt_anchor);
+            const hipError_t eq =
+                enqueue_sweep(P, T, ws, cfg.grid, cfg.dynamic != 0, c->cap, c->opt_anchor, c->opt_one_launch);
             hipGraph_t graph = nullptr;
             const hipError_t ee = hipStreamEndCapture(c->cap, &graph);
             HIPCHK(c, eq);
@@ -964,11 +1070,39 @@ int pst_label_f1(pst_ctx *ctx, const int32_t *owner_dev, int64_t n, int32_t m, i
     return PST_OK;
 }
 
+int pst_tune_geometry(pst_ctx *ctx, const double *T_dev, int64_t n, int32_t m, int32_t l, int32_t *code_out,
+                      float *ms_out, void *ws_dev, size_t ws_bytes) {
+    int rc = begin(ctx);
+    if (rc) return rc;
+    Layout L;
+    if ((rc = plan(ctx, n, m, l, 0, 1, &L))) return rc;
+    if (!T_dev || !code_out) return fail(ctx, PST_EINVAL, "null pointer argument");
+    if ((rc = check_ws(ctx, L, ws_dev, ws_bytes))) return rc;
+    char *ws = (char *)ws_dev;
+    if ((rc = series_stats(ctx, T_dev, ws + L.o_T, L.sT, "T"))) return rc;
+    float ms = 0.0f;
+    if ((rc = tune_geometry_job(ctx, job_for(L, ws, (float *)(ws + L.o_D), L.Nm, nullptr), code_out, &ms)))
+        return rc;
+    if (ms_out) *ms_out = ms;
+    return PST_OK;
+}
+
+int pst_geometry_candidates(int32_t w, int32_t *codes, int32_t max) {
+    if (max < 0 || (max > 0 && !codes)) return PST_EINVAL;
+    return profile_geometry_candidates(w, codes, max);
+}
+
+int32_t pst_geometry(int32_t w) { return w >= 1 && w <= kMaxW ? profile_geometry(w) : 0; }
+
+int pst_set_geometry(int32_t w, int32_t code) { return profile_set_geometry(w, code) ? PST_OK : PST_EINVAL; }
+
 int pst_set_option(pst_ctx *ctx, int option, int64_t value) {
     if (!ctx) return PST_EINVAL;
     switch (option) {
         case PST_OPT_SWEEP_GRAPH: ctx->opt_graph = value != 0; break;
         case PST_OPT_AUTOTUNE: ctx->opt_autotune = value != 0; break;
+        case PST_OPT_TUNE_GEOMETRY: ctx->opt_tune_geometry = value != 0; break;
+        case PST_OPT_SWEEP_ONE_LAUNCH: ctx->opt_one_launch = value != 0; break;
         case PST_OPT_PROFILE_GRID:
             if (value < 0 || value > 4096) return fail(ctx, PST_EINVAL, "grid out of range");
             ctx->opt_grid = (int)value;
@@ -1208,6 +1342,18 @@ int pst_select_length(pst_ctx *ctx, const double *T_dev, int64_t n, const int32_
         if (((uintptr_t)ws & 255) != 0) return fail(ctx, PST_EINVAL, "workspace must be 256-byte aligned");
         if (ws_bytes < P.total)
             return fail(ctx, PST_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, P.total);
+        if (ctx->opt_tune_geometry) {  // tile geometry of every length, then the shapes again
+            for (size_t j = 0; j < P.ls.size(); ++j)
+                HIPCHK(ctx, launch_series_stats(T_dev, ws + P.o_stats[j], P.SL[j], ctx->stream));
+            ProfileJob jobs[kMaxJobs];
+            const int nj = sweep_jobs(P, ws, P.grid, jobs, 0);
+            for (int j = 0; j < nj; ++j) {
+                int32_t code = 0;
+                float ms = 0.0f;
+                if ((rc = tune_geometry_job(ctx, jobs[j], &code, &ms))) return rc;
+            }
+            sweep_shapes(&P);
+        }
         std::vector<double> res;
         if ((rc = run_sweep(ctx, P, T_dev, ws, ws_bytes, m_list, l_list, &res))) return rc;
         const int S = P.out_stride;

@@ -76,6 +76,17 @@ int32_t profile_grid(int64_t tiles, int32_t w);   // persistent grid for that ma
 size_t profile_scratch_floats(int32_t grid, int32_t w);
 hipError_t launch_profile(const ProfileJob &job, hipStream_t st);
 size_t profile_lds_bytes(int32_t w);   // dynamic LDS of one profile workgroup
+// Tile geometry of the profile kernel for w (workgroup size, diagonals per
+// thread, rows per chunk, selection threads, sub-tile width) as one code: the
+// one in use, the candidates the kernels can run, and an override for w
+// (code 0 restores the built-in choice; false if the code is not a
+// candidate).  Results of different geometries agree within the profile
+// tolerance, not bit for bit (sub-tiles anchor their diagonals afresh).
+int32_t profile_geometry(int32_t w);
+int32_t profile_geometry_candidates(int32_t w, int32_t *codes, int32_t max);
+bool profile_set_geometry(int32_t w, int32_t code);
+// Profile scratch floats that any candidate geometry needs for nq queries.
+size_t profile_scratch_bound(int64_t Nm, int64_t nq, int32_t w);
 
 // Greedy snippet search and its by-products, all on device (eqs. 6-8, 16-18).
 struct GreedyJob {

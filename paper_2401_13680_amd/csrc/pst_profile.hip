@@ -47,6 +47,9 @@
 // segments get bit-identical profiles.
 #include "pst_internal.h"
 
+#include <algorithm>
+#include <atomic>
+
 #include <math.h>
 
 // A build with -DPST_PROBE (build.py --probe, libpst_probe.so) measures, per
@@ -1006,7 +1009,7 @@ bool geometry_ok(int w, const Geo &g) {
 
 // Two 256-thread workgroups per CU where their LDS fits (so one can select
 // while the other computes), else one of 512 threads.
-Geo geo_for(int w) {
+Geo geo_heuristic(int w) {
     Geo g;
     g.NT = 256;
     g.nA = 256;
@@ -1035,16 +1038,80 @@ Geo geo_for(int w) {
     return g;
 }
 
+// A geometry as one number: threads/256 << 24 | V << 16 | RCH << 8 |
+// nA/256 << 4 | SBW/(32 G).
+int32_t geo_code(const Geo &g) {
+    return ((g.NT / 256) << 24) | (g.V << 16) | (g.RCH << 8) | ((g.nA / 256) << 4) | (g.SBW / (32 * G));
+}
+Geo geo_decode(int32_t c) {
+    Geo g;
+    g.NT = ((c >> 24) & 0xF) * 256;
+    g.V = (c >> 16) & 0xFF;
+    g.RCH = (c >> 8) & 0xFF;
+    g.nA = ((c >> 4) & 0xF) * 256;
+    g.SBW = (c & 0xF) * 32 * G;
+    g.JT = g.nA * G;
+    return g;
+}
+
+// Every geometry the instantiated kernels can run for w: (threads, diagonals
+// per thread, rows per chunk) of a kernel, 256 or 512
+// selection threads (at most the workgroup's), sub-tiles of 992 or 1984
+// windows, within the limits of geometry_ok.
+int geo_candidates(int w, int32_t *codes, int max) {
+    static const int kern[][3] = {{256, 5, 8}, {256, 6, 8}, {512, 5, 8}, {512, 5, 4}, {512, 6, 4}};
+    int n = 0;
+    for (const auto &k : kern)
+        for (int na = 256; na <= k[0]; na += 256)
+            for (int sb = 1; sb <= 2; ++sb) {
+                Geo g;
+                g.NT = k[0];
+                g.V = k[1];
+                g.RCH = k[2];
+                g.nA = na;
+                g.SBW = sb * 32 * G;
+                g.JT = na * G;
+                if (!geometry_ok(w, g)) continue;
+                if (n < max) codes[n] = geo_code(g);
+                ++n;
+            }
+    return n;
+}
+
+// Geometries chosen by the autotuner, per w (0: the heuristic).
+std::atomic<int32_t> g_geo_code[kMaxW + 1];
+
+Geo geo_for(int w) {
+    const int32_t c = w >= 1 && w <= kMaxW ? g_geo_code[w].load(std::memory_order_relaxed) : 0;
+    return c ? geo_decode(c) : geo_heuristic(w);
+}
+
 }  // namespace
+
+int32_t profile_geometry(int32_t w) { return geo_code(geo_for(w)); }
+
+int32_t profile_geometry_candidates(int32_t w, int32_t *codes, int32_t max) {
+    return w >= 1 && w <= kMaxW ? geo_candidates(w, codes, max) : 0;
+}
+
+bool profile_set_geometry(int32_t w, int32_t code) {
+    if (w < 1 || w > kMaxW) return false;
+    if (code != 0) {
+        int32_t c[64];
+        const int n = geo_candidates(w, c, 64);
+        bool ok = false;
+        for (int i = 0; i < n && i < 64; ++i) ok |= c[i] == code;
+        if (!ok) return false;
+    }
+    g_geo_code[w].store(code, std::memory_order_relaxed);
+    return true;
+}
 
 int32_t profile_tile_windows(int32_t w) { return geo_for(w).JT; }
 
 int32_t profile_slots(int32_t w) { return kCUs * (512 / geo_for(w).NT); }
 
-int32_t profile_shape(int32_t w) {
-    const Geo g = geo_for(w);
-    return ((g.NT / 256) << 24) | (g.V << 16) | (g.RCH << 8) | ((g.nA / 256) << 4) | (g.SBW / (32 * G));
-}
+int32_t profile_shape(int32_t w) { return geo_code(geo_for(w)); }
 
 int32_t profile_grid(int64_t tiles, int32_t w) {
     const int64_t slots = profile_slots(w);
@@ -1053,9 +1120,28 @@ int32_t profile_grid(int64_t tiles, int32_t w) {
 
 // scratch floats of one workgroup: the row minima of a tile, then the tile's
 // column minima
-static size_t slot_floats_for(int32_t w) {
-    const size_t JT = (size_t)geo_for(w).JT;
+static size_t slot_floats_geo(int32_t w, const Geo &g) {
+    const size_t JT = (size_t)g.JT;
     return (size_t)w * JT + ((JT + w - 1 + 3) & ~(size_t)3);
+}
+static size_t slot_floats_for(int32_t w) { return slot_floats_geo(w, geo_for(w)); }
+
+// The largest profile scratch any candidate geometry needs for nq queries of
+// Nm windows at w (workspaces are sized with it, so that a geometry chosen
+// later still fits).
+size_t profile_scratch_bound(int64_t Nm, int64_t nq, int32_t w) {
+    int32_t c[64];
+    const int n = std::min(geo_candidates(w, c, 64), 64);
+    size_t best = 0;
+    auto one = [&](const Geo &g) {
+        const int64_t tiles = ((Nm + g.JT - 1) / g.JT) * nq;
+        const int64_t slots = kCUs * (512 / g.NT);
+        const int64_t grid = std::max<int64_t>(1, std::min(tiles, slots));
+        best = std::max(best, (size_t)grid * slot_floats_geo(w, g));
+    };
+    for (int i = 0; i < n; ++i) one(geo_decode(c[i]));
+    one(geo_heuristic(w));
+    return best;
 }
 
 size_t profile_scratch_floats(int32_t grid, int32_t w) { return (size_t)grid * slot_floats_for(w); }
