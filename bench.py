@@ -90,10 +90,13 @@ def cpu_baseline(x, m, l, k, nseg_sample=20):
                        f"{dt:.1f} s), numpy FP64, BLAS limited to 1 thread")
 
 
-PROBE_NAMES = {0: "windows", 1: "run_starts", 2: "windows_by_own_pass", 3: "cooperative_selects"}
+PROBE_NAMES = {0: "windows", 1: "run_starts", 2: "windows_by_own_pass", 3: "cooperative_selects",
+               4: "misses_below", 5: "misses_above", 6: "list_overflows", 7: "misses_at_run_start",
+               8: "overflows_of_one_key_brackets", 9: "sum_of_list_lengths", 10: "overflows_holding_kth",
+               11: "second_pass_brackets", 12: "windows_by_second_pass"}
 PROBE_PHASES = {16: "distance phase", 17: "  FP64 anchors", 18: "  FP32 recurrence", 19: "  column minima",
                 20: "  sliding row minima", 21: "selection phase", 22: "  run starts (radix select)",
-                23: "  bracket passes", 24: "  sorts", 25: "  cooperative selects"}
+                23: "  bracket passes", 24: "  sorts and second passes", 25: "  cooperative selects"}
 
 
 def probe_bench(args):
@@ -128,6 +131,47 @@ def probe_bench(args):
                wave_cycles={v.strip(): int(buf[k]) for k, v in PROBE_PHASES.items()},
                share_of_wave_time={v.strip(): round(buf[k] / tot, 4) for k, v in PROBE_PHASES.items()})
     print(json.dumps(out), flush=True)
+
+
+def geometry_bench(args):
+    """Every tile geometry of the profile kernel, per m of the serving stream
+    (m in {64, .., 1024}, l = m/2): all segment profiles of a 200 000-point
+    five-shape series, three launches each after a warm-up, against the
+    built-in choice and the tuner's."""
+    import torch
+
+    from paper_2401_13680_amd import api, synth
+
+    n = 200_000
+    out = {}
+    for m in (64, 128, 256, 512, 1024):
+        l = m // 2
+        w = m - l + 1
+        T = torch.from_numpy(synth.regime_series(n, 70 + m, len_range=(2000, 8000)).x).cuda()
+
+        def t_profile():
+            api.profile_set(T, m, l)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(3):
+                api.profile_set(T, m, l)
+            torch.cuda.synchronize()
+            return (time.perf_counter() - t0) / 3 * 1e3
+
+        base = t_profile()
+        res = {}
+        for code in api.geometry_candidates(w):
+            api.set_geometry(w, code)
+            res[hex(code)] = round(t_profile(), 2)
+        api.set_geometry(w, 0)
+        code, _ = api.tune_geometry(T, m, l)
+        tuned = t_profile()
+        api.set_geometry(w, 0)
+        cells = (n // m) * w * (n - l + 1)
+        out[m] = dict(w=w, builtin=hex(api.geometry(w)), builtin_ms=round(base, 2), tuned=hex(code),
+                      tuned_ms=round(tuned, 2), all_ms=res, builtin_cells_per_s=cells / base * 1e3)
+        progress(f"m={m}: built-in {base:.1f} ms, tuned {tuned:.1f} ms")
+    print(json.dumps(dict(workload="geometries_regimes5_n200000", per_m=out)), flush=True)
 
 
 def sweep_bench(args):
@@ -603,7 +647,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="serve",
-                    choices=["serve", "plain", "serve_order", "sweep", "multi", "schedule", "blocked", "probe"])
+                    choices=["serve", "plain", "serve_order", "sweep", "multi", "schedule", "blocked", "probe",
+                             "geometry"])
     ap.add_argument("--requests", type=int, default=40, help="serve_order: number of requests")
     ap.add_argument("--probe-m", type=int, default=0, help="probe: snippet length (l = m/2)")
     ap.add_argument("--probe-geometry", default="", help="probe: tile geometry code to install first")
@@ -630,6 +675,8 @@ def main():
         return blocked_bench(args)
     if args.workload == "probe":
         return probe_bench(args)
+    if args.workload == "geometry":
+        return geometry_bench(args)
 
     import numpy as np
     import torch

@@ -81,6 +81,11 @@ constexpr int kStageIters = 5;   // column-statistics entries per thread per sub
 constexpr int CAP = 28;    // sorted candidate list capacity
 constexpr int NB = 16;     // radix buckets per level
 constexpr int BAND = 8;    // bracket half-width in ranks
+// A wave runs the second bracket pass only when at least this many of its
+// lanes missed: the pass costs the whole wave a pass, a cooperative select
+// costs it a fraction of one (thresholds 1, 2, 3, 4 and 6 measured on w = 33
+// .. 513: 3 and 4 fastest, 1 up to 9 % slower).
+constexpr int RETRY_MIN = 3;
 constexpr int BL = 32;     // values per load batch of a window pass
 constexpr int BMW = 128;   // block minima per row (two blocks per lane at most)
 constexpr int RPAD = 32;   // LDS floats after the row buffer (row-minimum reads past a row end)
@@ -307,6 +312,36 @@ struct Coop {
     uint32_t *sorted; // CAP keys
 };
 constexpr int COOP_FLOATS = NB + 4 + 2 * CAP;
+
+// Exact ranks r1 .. r2 (1-based) of one window's 2w values for w <= 64, by
+// the 64 lanes of a wave together: lane x holds A(x) = ab[x * gs] and B(x) =
+// bv[x] and counts, for both, the values smaller than it, ties by position
+// (the A values first, in row order, then the B values in column order); the
+// other lanes' values come from their registers.  The values of ranks r1 ..
+// r2 land in C.sorted in order; *below = r1 - 1.  A few hundred instructions,
+// where the radix select takes several rounds of histograms.  Must be called
+// by all lanes of the wave.
+__device__ __forceinline__ int coop_rank(const float *ab, int gs, const float *bv, int w, int r1, int r2,
+                                         const Coop &C, int lane, int *below) {
+    const bool in = lane < w;
+    const uint32_t a = in ? key_of(ab[(size_t)lane * gs]) : 0xFFFFFFFFu;  // outside: never counted
+    const uint32_t b = in ? ((const uint32_t *)bv)[lane] : 0xFFFFFFFFu;
+    int ra = 0, rb = 0;
+    // valid keys are at most 0x7F800000, so key + 1 does not wrap
+#pragma unroll 2
+    for (int src = 0; src < w; ++src) {
+        const uint32_t va = (uint32_t)__builtin_amdgcn_readlane((int)a, src);
+        const uint32_t vb = (uint32_t)__builtin_amdgcn_readlane((int)b, src);
+        const uint32_t lower = src < lane;
+        ra += (va < a + lower) + (vb < a);   // A(src) before A(lane); every B after
+        rb += (va <= b) + (vb < b + lower);  // every A before B(lane); B(src) before it
+    }
+    if (in && ra >= r1 - 1 && ra <= r2 - 1) C.sorted[ra - r1 + 1] = a;
+    if (in && rb >= r1 - 1 && rb <= r2 - 1) C.sorted[rb - r1 + 1] = b;
+    wave_sync();
+    *below = r1 - 1;
+    return r2 - r1 + 1;
+}
 
 // Exact radix select, by the 64 lanes of a wave together, of the key range
 // holding ranks r1 .. r2 (1-based) of one window's 2w values: A(i) =
@@ -894,44 +929,129 @@ __global__ void __launch_bounds__(NT, 2) k_profile(ProfileArgs A) {
                 }
                 PROBE_SPAN(22, tRun);
                 PROBE_MARK(tPass);
-                Bracket<NT> Bk{blo, bhi - blo, 0, 0, L};
-                window_pass(R, voff, rstr, colY + v, w, Bk);
-                const int kk = keff - Bk.below, nl = Bk.nl;
-                const bool ok = kk >= 1 && kk <= nl && nl <= CAP;
+                // Results of the last pass of this window: its bracket [plo,
+                // phi], the values under it (pb) and in it (pn), the rank of
+                // the k-th among those in it (pk); L holds them sorted.
+                uint32_t plo = blo, phi = bhi;
+                int pb, pn, pk;
+                auto pass = [&](uint32_t lo, uint32_t hi) {
+                    Bracket<NT> Bk{lo, hi - lo, 0, 0, L};
+                    window_pass(R, voff, rstr, colY + v, w, Bk);
+                    plo = lo;
+                    phi = hi;
+                    pb = Bk.below;
+                    pn = Bk.nl;
+                    pk = keff - pb;
+                    uint32_t srt[CAP];
+#pragma unroll
+                    for (int x = 0; x < CAP; ++x) srt[x] = x < pn ? L[x * NT] : 0xFFFFFFFFu;
+                    sort_net(srt);
+#pragma unroll
+                    for (int x = 0; x < CAP; ++x) L[x * NT] = srt[x];
+                };
+                // the pass held rank k: in its list, or, for a bracket of one
+                // key, in a list that overflowed (every value in it is that key)
+                auto held = [&]() { return pk >= 1 && pk <= pn && (pn <= CAP || plo == phi); };
+                // rank k, and the next bracket: ranks k-BAND .. k+BAND of this
+                // window, or extrapolated from the list's spacing where it ends
+                auto take = [&]() {
+                    if (pn > CAP) {  // one-key bracket: keep it
+                        ystar = plo;
+                        blo = bhi = plo;
+                        return;
+                    }
+                    ystar = L[(pk - 1) * NT];
+                    const int q1 = r1 - pb, q2 = r2 - pb;
+                    const float l0 = __uint_as_float(L[0]), l1 = __uint_as_float(L[(pn - 1) * NT]);
+                    const float sp = (l1 - l0) / (float)max(pn - 1, 1);
+                    blo = q1 >= 1 ? L[(q1 - 1) * NT] : key_of(fmaxf(l0 - 1.5f * (float)(1 - q1) * sp, 0.0f));
+                    bhi = q2 <= pn ? L[(q2 - 1) * NT] : key_of(l1 + 1.5f * (float)(q2 - pn) * sp);
+                };
+                pass(blo, bhi);
+                bool ok = held();
                 PROBE_SPAN(23, tPass);
                 PROBE_MARK(tSort);
                 PROBE(2, valid && ok);
-                uint32_t srt[CAP];
-#pragma unroll
-                for (int x = 0; x < CAP; ++x) srt[x] = x < nl ? L[x * NT] : 0xFFFFFFFFu;
-                sort_net(srt);
-#pragma unroll
-                for (int x = 0; x < CAP; ++x) L[x * NT] = srt[x];
-                PROBE_SPAN(24, tSort);
-                if (ok) {
-                    ystar = L[(kk - 1) * NT];
-                    // next bracket: ranks k-BAND .. k+BAND of this window, or
-                    // extrapolated from the list's spacing where it ends early
-                    const int q1 = r1 - Bk.below, q2 = r2 - Bk.below;
-                    const float l0 = __uint_as_float(L[0]), l1 = __uint_as_float(L[(nl - 1) * NT]);
-                    const float sp = (l1 - l0) / (float)max(nl - 1, 1);
-                    blo = q1 >= 1 ? L[(q1 - 1) * NT] : key_of(fmaxf(l0 - 1.5f * (float)(1 - q1) * sp, 0.0f));
-                    bhi = q2 <= nl ? L[(q2 - 1) * NT] : key_of(l1 + 1.5f * (float)(q2 - nl) * sp);
+                PROBE(4, valid && !ok && pk < 1);
+                PROBE(5, valid && !ok && pk > pn && pn <= CAP);
+                PROBE(6, valid && pn > CAP);
+                PROBE(7, valid && !ok && p == 0);
+                PROBE(8, valid && pn > CAP && plo == phi);
+                PROBE(9, valid ? pn : 0);
+                PROBE(10, valid && pn > CAP && pk >= 1 && pk <= pn);
+                if (ok) take();
+                // A bracket that missed rank k gets one more pass, by all such
+                // lanes of the wave at once (when there are RETRY_MIN of
+                // them), with a bracket re-aimed at ranks
+                // k-BAND .. k+BAND: under it, everything (when that is few
+                // values) or the list's spacing extrapolated down from it;
+                // over it, the spacing extrapolated up; inside an
+                // overflowing list, the stretch of the list (a sample of the
+                // bracket's values) around rank k's share.  A second miss
+                // goes to the wave's cooperative select.
+                // Lanes without a second pass repeat their first one (the
+                // next window's bracket, or the same missed bracket), so that
+                // a missed bracket's counts stay what the select starts from.
+                // A bracket must satisfy lo <= hi: the pass relies on
+                // hi - lo < 2^31.
+                uint32_t rlo = blo, rhi = bhi;
+                bool retry = false;
+                if (valid && !ok) {
+                    const int nk = min(pn, CAP);  // sorted values in L
+                    const float l0 = __uint_as_float(L[0]), l1 = __uint_as_float(L[(max(nk, 1) - 1) * NT]);
+                    // spacing of the values near the bracket: the list's, or
+                    // the bracket's width over the band where the list is short
+                    const float sp = nk >= 2 && l1 > l0
+                                         ? (l1 - l0) / (float)(nk - 1)
+                                         : (__uint_as_float(phi) - __uint_as_float(plo)) / (float)(2 * BAND);
+                    uint32_t tlo = 1u, thi = 0u;
+                    if (pn > CAP) {  // overflow around rank k: the list is a sample of the bracket
+                        if (pk >= 1 && pk <= pn) {
+                            const int q = (pk - 1) * CAP / pn, d = max(1, (BAND + 2) * CAP / pn);
+                            tlo = q - d <= 0 ? plo : L[(q - d) * NT];
+                            thi = q + d >= CAP - 1 ? phi : L[(q + d) * NT];
+                        }
+                    } else if (pk < 1) {  // rank k under the bracket, pb values there
+                        const bool all = pb <= CAP && r2 <= CAP;
+                        if (all || sp > 0.0f) {
+                            tlo = all ? 0u
+                                      : key_of(fmaxf(__uint_as_float(plo) - 1.5f * (float)(pb - r1 + 2) * sp, 0.0f));
+                            thi = r2 <= pb ? plo - 1u : (r2 - pb <= pn ? L[(r2 - pb - 1) * NT] : phi);
+                        }
+                    } else if (sp > 0.0f) {  // rank k over the bracket
+                        tlo = r1 <= pb ? plo : (r1 - pb <= pn ? L[(r1 - pb - 1) * NT] : phi + 1u);
+                        thi = key_of(__uint_as_float(phi) + 1.5f * (float)(r2 - pb - pn + 1) * sp);
+                    }
+                    if (tlo <= thi) {
+                        rlo = tlo;
+                        rhi = thi;
+                        retry = true;
+                    }
                 }
-                // where the k-th value lies, from this pass: below the bracket,
-                // above it, or inside an overflowing list
-                uint32_t flo = 0u, fhi = bhi + 1u;
+                PROBE(11, retry);
+                if (__popcll(__ballot(retry)) >= RETRY_MIN) {
+                    pass(rlo, rhi);
+                    if (retry && held()) {
+                        ok = true;
+                        take();
+                    }
+                    PROBE(12, retry && ok);
+                }
+                // where the k-th value lies, from the last pass: below its
+                // bracket, above it, or inside an overflowing list
+                uint32_t flo = 0u, fhi = phi + 1u;
                 int fbase = 0;
-                if (kk > nl) {
-                    flo = bhi + 1u;
+                if (pk > pn) {
+                    flo = phi + 1u;
                     fhi = 0x7F800000u;
-                    fbase = Bk.below + nl;
-                } else if (kk >= 1) {
-                    flo = blo;
-                    fbase = Bk.below;
+                    fbase = pb + pn;
+                } else if (pk >= 1) {
+                    flo = plo;
+                    fbase = pb;
                 } else {
-                    fhi = blo;
+                    fhi = plo;
                 }
+                PROBE_SPAN(24, tSort);
                 PROBE_MARK(tCoop);
                 uint64_t need = __ballot(valid && !ok);
                 while (need) {
@@ -941,14 +1061,31 @@ __global__ void __launch_bounds__(NT, 2) k_profile(ProfileArgs A) {
                     int below = 0;
                     const uint32_t clo = (uint32_t)__shfl((int)flo, ln), chi = (uint32_t)__shfl((int)fhi, ln);
                     const int cbase = __shfl(fbase, ln);
-                    const int nc = coop_band(rw + p * pstr + tf, nA, colY + tf * G + p, w, keff, r1, r2,
-                                             clo, chi, cbase, C, lane, &below);
+                    // short windows: the band's ranks counted outright;
+                    // longer ones: a radix select from the failed pass's range
+                    const float *ab = rw + p * pstr + tf, *bw = colY + tf * G + p;
+                    const bool by_rank = w <= 64;
+                    const int nc = by_rank ? coop_rank(ab, nA, bw, w, r1, r2, C, lane, &below)
+                                           : coop_band(ab, nA, bw, w, keff, r1, r2, clo, chi, cbase, C, lane,
+                                                       &below);
                     if (lane == ln) {
                         PROBE(3, 1);
                         const int kk2 = keff - below;
                         ystar = C.sorted[min(max(kk2, 1), nc) - 1];
-                        blo = C.sorted[min(max(r1 - below, 1), nc) - 1];
-                        bhi = C.sorted[min(max(r2 - below, 1), nc) - 1];
+                        uint32_t nlo = C.sorted[min(max(r1 - below, 1), nc) - 1];
+                        uint32_t nhi = C.sorted[min(max(r2 - below, 1), nc) - 1];
+                        // The radix select searched only the side of the
+                        // last bracket that holds rank k.  Ranks of the next
+                        // bracket on the other side come from that pass (its
+                        // sorted list, or the bracket's end), so that the next
+                        // bracket spans ranks k-BAND .. k+BAND again instead of
+                        // shrinking to the searched side.
+                        if (!by_rank && pn <= CAP && pk < 1 && r2 > pb)
+                            nhi = r2 - pb <= pn ? L[(r2 - pb - 1) * NT] : phi;
+                        if (!by_rank && pn <= CAP && pk > pn && r1 <= pb + pn)
+                            nlo = r1 > pb ? L[(r1 - pb - 1) * NT] : plo;
+                        blo = nlo;
+                        bhi = nhi;
                     }
                     wave_sync();
                 }
@@ -1201,10 +1338,16 @@ hipError_t launch_profile(const ProfileJob &job, hipStream_t st) {
 
 #ifdef PST_PROBE
 // Sums of the probe counters since the last reset: 0 windows, 1 run starts,
-// 2 windows solved by their own bracket pass, 3 cooperative selects; wave
+// 2 windows solved by their own bracket pass, 3 cooperative selects, 4-7
+// misses with the k-th value below the bracket, above it, with an
+// overflowing list, at a run's first window; 8 overflows of a one-key
+// bracket, 9 the sum of the list lengths, 10 overflows that held the k-th
+// value, 11 windows with a second-pass bracket, 12 windows a second pass
+// solved; wave
 // cycles of 16 the distance phase, 17 FP64 anchors, 18 the FP32 recurrence,
 // 19 column minima, 20 sliding row minima, 21 the selection phase, 22 run
-// starts, 23 bracket passes, 24 sorts, 25 cooperative selects.
+// starts, 23 first bracket passes, 24 sorts and second passes, 25 cooperative
+// selects.
 extern "C" int pst_probe_read(unsigned long long *out, int reset) {
     static unsigned long long buf[32 * 64];
     if (hipMemcpyFromSymbol(buf, HIP_SYMBOL(g_probe), sizeof(buf)) != hipSuccess) return -3;

@@ -1,6 +1,6 @@
 """Write expected snippet results computed by the CPU oracle (oracle/ only).
 
-    python tests/golden/make_golden.py [name ...] [--procs N]
+    python tests/golden/make_golden.py [name ...] [--procs N] [--resume FILE]
 
 Each output file holds the oracle's snippet records, areas, per-step greedy
 margins (second-best area minus best) and the runner-up segment of every
@@ -81,7 +81,7 @@ def profile_set_pool(pool, x, m, l, k, procs, use):
     nseg, Nm = len(x) // m, len(x) - m + 1
     shm = shared_memory.SharedMemory(create=True, size=nseg * Nm * 8)
     try:
-        nchunk = max(procs * 4, nseg // 16)
+        nchunk = max(procs * 4, nseg // 2)  # two segments per task bound a worker's memory
         chunks = [list(range(i, nseg, nchunk)) for i in range(nchunk)]
         chunks = [c for c in chunks if c]
         pool.map(_rows, [(m, l, k, c, shm.name, (nseg, Nm)) for c in chunks], chunksize=1)
@@ -121,18 +121,30 @@ def make(name, procs=8):
     return out
 
 
-def make_sweep(name, procs=8):
+def make_sweep(name, procs=8, resume=None):
+    """resume: a JSON-lines file that keeps each finished length, so that an
+    interrupted run continues where it stopped."""
     c = SWEEPS[name]
     x = c["series"]()
     K = c["K"]
     path = os.path.join(HERE, f"sweep_{name}.json")
-    per = []
-    with Pool(procs, initializer=_init, initargs=(x,)) as pool:
-        for m in c["m_list"]:
+    done = {}
+    if resume and os.path.exists(resume):
+        for line in open(resume):
+            r = json.loads(line)
+            done[r["m"]] = r
+    # longest lengths first: they take the most memory and time
+    todo = sorted((m for m in c["m_list"] if m not in done), reverse=True)
+    with Pool(procs, initializer=_init, initargs=(x,), maxtasksperchild=16) as pool:
+        for m in todo:
             l = m // 2
-            per.append(profile_set_pool(pool, x, m, l, oracle.default_k(m), procs,
-                                        lambda D: one_length(x, m, l, K, D)))
-            print(name, "m", m, "picks", per[-1]["picks"], "score", per[-1]["score"], flush=True)
+            done[m] = profile_set_pool(pool, x, m, l, oracle.default_k(m), procs,
+                                       lambda D: one_length(x, m, l, K, D))
+            print(name, "m", m, "picks", done[m]["picks"], "score", done[m]["score"], flush=True)
+            if resume:
+                with open(resume, "a") as f:
+                    f.write(json.dumps(done[m]) + "\n")
+    per = [done[m] for m in c["m_list"]]
     scores = [p["score"] for p in per]
     ms = [p["m"] for p in per]
     # eq. 18: the largest score, ties to the smallest m (as oracle.select_length)
@@ -148,14 +160,18 @@ def make_sweep(name, procs=8):
 
 if __name__ == "__main__":
     args = sys.argv[1:]
-    procs = 8
+    procs, resume = 8, None
     if "--procs" in args:
         i = args.index("--procs")
         procs = int(args[i + 1])
         del args[i:i + 2]
+    if "--resume" in args:
+        i = args.index("--resume")
+        resume = args[i + 1]
+        del args[i:i + 2]
     for name in args or list(CASES):
         if name in SWEEPS:
-            o = make_sweep(name, procs)
+            o = make_sweep(name, procs, resume)
             print(name, "m_best", o["m_best"], flush=True)
         else:
             o = make(name, procs)
