@@ -1156,11 +1156,8 @@ Geo geo_heuristic(int w) {
     g.V = g.SBW + 2 * w - 2 + 4 <= 5 * 256 ? 5 : 6;
     if (geometry_ok(w, g)) return g;
     g.NT = 512;
-    if (w <= 257) {
+    if (w <= 513) {  // all threads select: fastest at w = 257 and 513 (of every candidate)
         g.nA = 512;
-        g.SBW = 64 * G;
-    } else if (w <= 513) {
-        g.nA = 256;
         g.SBW = 64 * G;
     } else {
         g.nA = 256;
