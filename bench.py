@@ -273,11 +273,7 @@ def multi_bench(args):
                config=dict(workload="multi4_n100000", n=n, d=d, m=m, l=l, K=K, cells_per_step=cells,
                            step="stats of every coordinate + all profiles in one launch + greedy + neighbours"),
                plain_one_coordinate_at_a_time=dict(value=cells / res["plain"][0], ms_per_step=res["plain"][0] * 1e3),
-               batched_over_plain=res["plain"][0] / dt,
-               one_launch_all_lengths=dict(value=cells / res["batched_graph_one_launch"][0],
-                                           ms_per_step=res["batched_graph_one_launch"][0] * 1e3,
-                                           m_best=res["batched_graph_one_launch"][1],
-                                           per_shape_over_one_launch=res["batched_graph_one_launch"][0] / dt), batched_equals_plain=same,
+               batched_over_plain=res["plain"][0] / dt, batched_equals_plain=same,
                labelling=dict(classes=C, macro_f1_per_coordinate=[round(v, 4) for v in f1]))
     print(json.dumps(out), flush=True)
 
