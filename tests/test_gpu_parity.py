@@ -188,9 +188,10 @@ def test_deterministic():
 
 def test_full_size_sampled_and_snippets():
     """The 100k-point, m=256 workload at full size: sampled profile entries
-    against the oracle one by one, and the snippets against the stored oracle
-    result with the margin-aware bound, computed from the oracle's rows of the
-    picks and runners-up of every step."""
+    (one window of every segment and more) against the oracle one by one, the
+    whole rows of the picks and runners-up against the oracle's rows, and the
+    snippets against the stored oracle result with the margin-aware bound,
+    computed from those rows."""
     gold = json.load(open(os.path.join(GOLDEN, "snippets_regimes5_n100000.json")))
     x = synth.regime_series(100_000, 2, synth.SHAPES5).x
     m, l, k, K = gold["m"], gold["l"], gold["k"], gold["K"]
@@ -199,6 +200,7 @@ def test_full_size_sampled_and_snippets():
     nseg, Nm = D.shape
     pairs = [(int(rng.integers(nseg)), int(rng.integers(Nm))) for _ in range(60)]
     pairs += [(s, s * m) for s in range(0, nseg, 97)] + [(nseg - 1, Nm - 1), (0, 0)]
+    pairs += [(s, int(rng.integers(Nm))) for s in range(nseg)]  # one window of every segment
     ref = oracle.mpdist_samples(x, m, l, k, pairs)
     Dg = D.cpu().numpy()
     got = np.array([Dg[s, j] for s, j in pairs])
@@ -210,6 +212,8 @@ def test_full_size_sampled_and_snippets():
     cands = sorted(set(gold["picks"]) | set(gold["runners"]) | set(picks))
     print(f"full size: oracle rows of segments {cands}", flush=True)
     Dr = oracle.profile_set(x, m, l, k, segments=cands)
+    # those whole rows too: every window of the series, entry by entry
+    assert_profiles_close(Dg[cands].astype(np.float64), Dr, l, "full-size oracle rows")
     rows_r = {s: Dr[i] for i, s in enumerate(cands)}
     rows_g = {s: Dg[s].astype(np.float64) for s in cands}
     res = check_greedy(picks, rows_g, rows_r, cands, "regimes5_n100000")
