@@ -319,12 +319,18 @@ int run_multi(pst_ctx *c, const MultiPlan &P, const double *T, int64_t ldT, char
         HIPCHK(c, hipEventRecord(c->ev1, c->stream));
         c->timed = true;
     }
-    for (int j = 0; j < P.d; ++j) {
-        GreedyJob g = greedy_for(L, region(j), (const float *)(region(j) + L.o_D), L.Nm);
-        g.owner = owner ? owner + (size_t)j * L.Nm : nullptr;
-        g.profiles = nullptr;
-        HIPCHK(c, launch_greedy(g, c->stream));
-        HIPCHK(c, launch_owner(g, c->stream));
+    // every coordinate's greedy search and neighbours in the same launches
+    for (int j0 = 0; j0 < P.d; j0 += kMaxJobs) {
+        GreedyJob gs[kMaxJobs];
+        const int nj = std::min(kMaxJobs, P.d - j0);
+        for (int i = 0; i < nj; ++i) {
+            const int j = j0 + i;
+            gs[i] = greedy_for(L, region(j), (const float *)(region(j) + L.o_D), L.Nm);
+            gs[i].owner = owner ? owner + (size_t)j * L.Nm : nullptr;
+            gs[i].profiles = nullptr;
+        }
+        HIPCHK(c, launch_greedy_batch(gs, nj, c->stream));
+        HIPCHK(c, launch_owner_batch(gs, nj, c->stream));
     }
     for (int j = 0; j < P.d; ++j) {
         const int rc = collect_records(c, L, region(j), out + (size_t)j * L.K, dmax_host ? dmax_host + j : nullptr,
@@ -681,10 +687,13 @@ hipError_t enqueue_sweep(const SweepPlan &P, const double *T, char *ws, int32_t 
     Gt.nm = P.nm;
     Gt.K = P.K;
     Gt.out = (double *)(ws + P.o_out);
+    // every length's greedy search and neighbours in the same launches
+    GreedyJob gs[kMaxJobs];
+    for (int i = 0; i < P.nm; ++i) gs[i] = sweep_greedy(P, i, ws);
+    if ((e = launch_greedy_batch(gs, P.nm, st)) != hipSuccess) return e;
+    if ((e = launch_owner_batch(gs, P.nm, st)) != hipSuccess) return e;
     for (int i = 0; i < P.nm; ++i) {
-        const GreedyJob G = sweep_greedy(P, i, ws);
-        if ((e = launch_greedy(G, st)) != hipSuccess) return e;
-        if ((e = launch_owner(G, st)) != hipSuccess) return e;
+        const GreedyJob &G = gs[i];
         if ((e = launch_criterion(G, st)) != hipSuccess) return e;
         Gt.crit[i] = G.crit + G.nblk2;
         Gt.dmax[i] = (const uint32_t *)(ws + P.gb[i].dmax);

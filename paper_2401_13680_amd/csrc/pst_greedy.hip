@@ -17,24 +17,9 @@ namespace {
 
 constexpr int GT = 256;
 
-__global__ void k_fill(float *__restrict__ p, int64_t n, float v) {
-    for (int64_t i = (int64_t)blockIdx.x * GT + threadIdx.x; i < n; i += (int64_t)gridDim.x * GT)
-        p[i] = v;
-}
-
-__global__ void k_zero_u8(uint8_t *__restrict__ p, int64_t n) {
-    for (int64_t i = (int64_t)blockIdx.x * GT + threadIdx.x; i < n; i += (int64_t)gridDim.x * GT)
-        p[i] = 0;
-}
-
 __global__ void k_set_u32(uint32_t *__restrict__ p, int64_t n, uint32_t v) {
     for (int64_t i = (int64_t)blockIdx.x * GT + threadIdx.x; i < n; i += (int64_t)gridDim.x * GT)
         p[i] = v;
-}
-
-__global__ void k_zero_i32(int32_t *__restrict__ p, int64_t n) {
-    for (int64_t i = (int64_t)blockIdx.x * GT + threadIdx.x; i < n; i += (int64_t)gridDim.x * GT)
-        p[i] = 0;
 }
 
 __device__ __forceinline__ double block_sum(double v, double *red) {
@@ -50,10 +35,34 @@ __device__ __forceinline__ double block_sum(double v, double *red) {
     return r;
 }
 
-// part[s * nblk + b] = sum over block b's windows of min(M_j, D_s(j)).
-__global__ void __launch_bounds__(GT) k_area_part(GreedyJob g) {
+// Greedy jobs of one launch: the grid's last dimension picks the job.
+struct GreedyBatch {
+    GreedyJob J[kMaxJobs];
+    int64_t part_end[kMaxJobs];  // job j owns area blocks [part_end[j-1], part_end[j])
+    int32_t n, kmax;
+};
+static_assert(sizeof(GreedyBatch) <= 4000, "kernel arguments must fit the 4 KB limit");
+
+// M = +inf and nothing chosen, for job blockIdx.y.
+__global__ void k_greedy_init(GreedyBatch B) {
+    const GreedyJob &g = B.J[blockIdx.y];
+    for (int64_t i = (int64_t)blockIdx.x * GT + threadIdx.x; i < g.Nm; i += (int64_t)gridDim.x * GT)
+        g.M[i] = INFINITY;
+    for (int64_t i = (int64_t)blockIdx.x * GT + threadIdx.x; i < g.nseg; i += (int64_t)gridDim.x * GT)
+        g.chosen[i] = 0;
+}
+
+// part[s * nblk + b] = sum over block b's windows of min(M_j, D_s(j)), one
+// workgroup per (job, segment, block), in round iter (jobs with fewer rounds
+// skip; iter < 0: no round check).
+__global__ void __launch_bounds__(GT) k_area_part(GreedyBatch B, int iter) {
     __shared__ double red[GT];
-    const int s = blockIdx.y, b = blockIdx.x;
+    int jb = 0;
+    while (jb + 1 < B.n && (int64_t)blockIdx.x >= B.part_end[jb]) ++jb;
+    const GreedyJob &g = B.J[jb];
+    const int64_t local = (int64_t)blockIdx.x - (jb ? B.part_end[jb - 1] : 0);
+    const int s = (int)(local / g.nblk), b = (int)(local - (int64_t)s * g.nblk);
+    if (iter >= 0 && iter >= g.K) return;
     if (g.chosen[s]) return;
     const int64_t j0 = (int64_t)b * kSumBlock;
     const int64_t j1 = j0 + kSumBlock < g.Nm ? j0 + kSumBlock : g.Nm;
@@ -64,10 +73,13 @@ __global__ void __launch_bounds__(GT) k_area_part(GreedyJob g) {
     if (threadIdx.x == 0) g.part[(int64_t)s * g.nblk + b] = tot;
 }
 
-// One block: smallest area among unchosen segments, ties to the lowest index.
-__global__ void __launch_bounds__(1024) k_pick(GreedyJob g, int iter) {
+// One block per job: smallest area among unchosen segments, ties to the
+// lowest index.
+__global__ void __launch_bounds__(1024) k_pick(GreedyBatch B, int iter) {
     __shared__ double ra[1024];
     __shared__ int rs[1024];
+    const GreedyJob &g = B.J[blockIdx.x];
+    if (iter >= g.K) return;
     const int t = threadIdx.x;
     double best = INFINITY;
     int bs = 0x7fffffff;
@@ -102,15 +114,23 @@ __global__ void __launch_bounds__(1024) k_pick(GreedyJob g, int iter) {
     }
 }
 
-__global__ void k_update_M(GreedyJob g, int iter) {
+__global__ void k_update_M(GreedyBatch B, int iter) {
+    const GreedyJob &g = B.J[blockIdx.y];
+    if (iter >= g.K) return;
     const float *Dp = g.D + (int64_t)g.pick[iter] * g.ld;
     for (int64_t j = (int64_t)blockIdx.x * GT + threadIdx.x; j < g.Nm; j += (int64_t)gridDim.x * GT)
         g.M[j] = fminf(g.M[j], Dp[j]);
 }
 
-__global__ void __launch_bounds__(GT) k_owner(GreedyJob g) {
+__global__ void k_zero_counts(GreedyBatch B) {
+    const GreedyJob &g = B.J[blockIdx.y];
+    for (int64_t i = (int64_t)blockIdx.x * GT + threadIdx.x; i < g.K; i += (int64_t)gridDim.x * GT) g.count[i] = 0;
+}
+
+__global__ void __launch_bounds__(GT) k_owner(GreedyBatch B) {
     extern __shared__ int cnt_lds[];
-    const bool use_lds = g.K <= 1024;
+    const GreedyJob &g = B.J[blockIdx.y];
+    const bool use_lds = B.kmax <= 1024;  // the launch sized LDS for every job's counts
     if (use_lds) {
         for (int p = threadIdx.x; p < g.K; p += GT) cnt_lds[p] = 0;
         __syncthreads();
@@ -187,44 +207,77 @@ hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_greedy(const GreedyJob &g, hipStream_t st) {
-    hipLaunchKernelGGL(k_fill, dim3(grid_for(g.Nm)), dim3(GT), 0, st, g.M, g.Nm, INFINITY);
-    hipLaunchKernelGGL(k_zero_u8, dim3(grid_for(g.nseg)), dim3(GT), 0, st, g.chosen, (int64_t)g.nseg);
-    for (int it = 0; it < g.K; ++it) {
-        hipLaunchKernelGGL(k_area_part, dim3(g.nblk, g.nseg), dim3(GT), 0, st, g);
-        hipLaunchKernelGGL(k_pick, dim3(1), dim3(1024), 0, st, g, it);
-        hipLaunchKernelGGL(k_update_M, dim3(grid_for(g.Nm)), dim3(GT), 0, st, g, it);
+namespace {
+GreedyBatch batch_of(const GreedyJob *g, int n) {
+    GreedyBatch B{};
+    B.n = n;
+    int64_t acc = 0;
+    for (int i = 0; i < n; ++i) {
+        B.J[i] = g[i];
+        acc += (int64_t)g[i].nseg * g[i].nblk;
+        B.part_end[i] = acc;
+        B.kmax = g[i].K > B.kmax ? g[i].K : B.kmax;
+    }
+    return B;
+}
+}  // namespace
+
+hipError_t launch_greedy_init(const GreedyJob &g, hipStream_t st) {
+    const GreedyBatch B = batch_of(&g, 1);
+    hipLaunchKernelGGL(k_greedy_init, dim3(grid_for(g.Nm > g.nseg ? g.Nm : g.nseg), 1), dim3(GT), 0, st, B);
+    return hipGetLastError();
+}
+
+hipError_t launch_greedy_batch(const GreedyJob *g, int n, hipStream_t st) {
+    if (n < 1 || n > kMaxJobs) return hipErrorInvalidValue;
+    const GreedyBatch B = batch_of(g, n);
+    int64_t span = 0;
+    for (int i = 0; i < n; ++i) {
+        span = g[i].Nm > span ? g[i].Nm : span;
+        span = g[i].nseg > span ? g[i].nseg : span;
+    }
+    const int64_t parts = B.part_end[n - 1];
+    if (parts < 1 || parts > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_greedy_init, dim3(grid_for(span), n), dim3(GT), 0, st, B);
+    for (int it = 0; it < B.kmax; ++it) {
+        hipLaunchKernelGGL(k_area_part, dim3((unsigned)parts), dim3(GT), 0, st, B, it);
+        hipLaunchKernelGGL(k_pick, dim3(n), dim3(1024), 0, st, B, it);
+        hipLaunchKernelGGL(k_update_M, dim3(grid_for(span), n), dim3(GT), 0, st, B, it);
     }
     return hipGetLastError();
 }
 
-hipError_t launch_greedy_init(const GreedyJob &g, hipStream_t st) {
-    hipLaunchKernelGGL(k_fill, dim3(grid_for(g.Nm)), dim3(GT), 0, st, g.M, g.Nm, INFINITY);
-    hipLaunchKernelGGL(k_zero_u8, dim3(grid_for(g.nseg)), dim3(GT), 0, st, g.chosen, (int64_t)g.nseg);
-    return hipGetLastError();
-}
+hipError_t launch_greedy(const GreedyJob &g, hipStream_t st) { return launch_greedy_batch(&g, 1, st); }
 
 hipError_t launch_area_parts(const GreedyJob &g, hipStream_t st) {
-    hipLaunchKernelGGL(k_area_part, dim3(g.nblk, g.nseg), dim3(GT), 0, st, g);
+    hipLaunchKernelGGL(k_area_part, dim3((unsigned)((int64_t)g.nseg * g.nblk)), dim3(GT), 0, st, batch_of(&g, 1),
+                       -1);
     return hipGetLastError();
 }
 
 hipError_t launch_pick(const GreedyJob &g, int iter, hipStream_t st) {
-    hipLaunchKernelGGL(k_pick, dim3(1), dim3(1024), 0, st, g, iter);
+    hipLaunchKernelGGL(k_pick, dim3(1), dim3(1024), 0, st, batch_of(&g, 1), iter);
     return hipGetLastError();
 }
 
 hipError_t launch_update_M(const GreedyJob &g, int iter, hipStream_t st) {
-    hipLaunchKernelGGL(k_update_M, dim3(grid_for(g.Nm)), dim3(GT), 0, st, g, iter);
+    hipLaunchKernelGGL(k_update_M, dim3(grid_for(g.Nm), 1), dim3(GT), 0, st, batch_of(&g, 1), iter);
     return hipGetLastError();
 }
 
-hipError_t launch_owner(const GreedyJob &g, hipStream_t st) {
-    hipLaunchKernelGGL(k_zero_i32, dim3(grid_for(g.K)), dim3(GT), 0, st, g.count, (int64_t)g.K);
-    const size_t lds = g.K <= 1024 ? sizeof(int) * g.K : 0;
-    hipLaunchKernelGGL(k_owner, dim3(grid_for(g.Nm)), dim3(GT), lds, st, g);
+hipError_t launch_owner_batch(const GreedyJob *g, int n, hipStream_t st) {
+    if (n < 1 || n > kMaxJobs) return hipErrorInvalidValue;
+    const GreedyBatch B = batch_of(g, n);
+    int64_t Nm = 1;
+    for (int i = 0; i < n; ++i) Nm = g[i].Nm > Nm ? g[i].Nm : Nm;
+    const int K = B.kmax > 1 ? B.kmax : 1;
+    hipLaunchKernelGGL(k_zero_counts, dim3(grid_for(K), n), dim3(GT), 0, st, B);
+    const size_t lds = K <= 1024 ? sizeof(int) * K : 0;
+    hipLaunchKernelGGL(k_owner, dim3(grid_for(Nm), n), dim3(GT), lds, st, B);
     return hipGetLastError();
 }
+
+hipError_t launch_owner(const GreedyJob &g, hipStream_t st) { return launch_owner_batch(&g, 1, st); }
 
 hipError_t launch_gather(const SweepGather &g, hipStream_t st) {
     hipLaunchKernelGGL(k_gather, dim3(1), dim3(256), 0, st, g);

@@ -106,6 +106,10 @@ struct GreedyJob {
     int32_t nblk2;
 };
 hipError_t launch_greedy(const GreedyJob &g, hipStream_t st);
+// Up to kMaxJobs greedy searches (and their neighbours) in the same launches,
+// one job per slice of each grid; every job's arithmetic is the same as alone.
+hipError_t launch_greedy_batch(const GreedyJob *g, int n, hipStream_t st);
+hipError_t launch_owner_batch(const GreedyJob *g, int n, hipStream_t st);
 // The greedy search's steps one by one (M = +inf and nothing chosen; the
 // area partials of g.nseg segments of g.D; the pick of round iter; M folded
 // with row g.pick[iter] of g.D), for callers that produce D in pieces.
