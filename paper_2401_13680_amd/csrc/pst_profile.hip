@@ -135,30 +135,51 @@ __device__ __forceinline__ void sort_net(uint32_t (&a)[N]) {
 
 // One thread's pass over the 2w values of a window: first A(i), i < w, the
 // row minima in the scratch buffer R (row i at byte offset voff + i * rstr);
-// then B(c) = bv[c], c < w, from LDS.  f(key, valid) sees every value once;
-// padding values of the last batch of each half come with valid = false.
-// Loads run a batch ahead of use.
+// then B(c) = bv[c], c < w, from LDS.  f(key, valid) sees every value once.
+// Values go in batches of BL, loads a batch ahead of use; the last batch of
+// each half stops at the group of GQ values that holds the half's end (w is
+// the same for the whole wave, so those checks are scalar branches), and its
+// padding values come with valid = false.  w = m/2 + 1 lies just past a
+// multiple of BL for the usual lengths, so whole padded batches would
+// almost double the work of short windows.
+constexpr int GQ = 8;
 template <typename F>
 __device__ __forceinline__ void window_pass(__amdgpu_buffer_rsrc_t R, uint32_t voff, uint32_t rstr, const float *bv,
                                             int w, F &&f) {
     const int wm1 = w - 1;
-    auto load = [&](uint32_t (&y)[BL], int i0) {
+    auto load_full = [&](uint32_t (&y)[BL], int i0) {  // rows i0 .. i0+BL-1, all inside
 #pragma unroll
-        for (int e = 0; e < BL; ++e) {
-            const int i = min(i0 + e, wm1);
-            y[e] = __builtin_amdgcn_raw_buffer_load_b32(R, (int)voff, (int)((uint32_t)i * rstr), 0);
+        for (int e = 0; e < BL; ++e)
+            y[e] = __builtin_amdgcn_raw_buffer_load_b32(R, (int)voff, (int)((uint32_t)(i0 + e) * rstr), 0);
+    };
+    auto load = [&](uint32_t (&y)[BL], int i0) {  // a batch that may hold the end
+        const int lim = w - i0;
+#pragma unroll
+        for (int q = 0; q < BL / GQ; ++q) {
+            if (q * GQ < lim) {
+#pragma unroll
+                for (int e = q * GQ; e < q * GQ + GQ; ++e) {
+                    const int i = min(i0 + e, wm1);
+                    y[e] = __builtin_amdgcn_raw_buffer_load_b32(R, (int)voff, (int)((uint32_t)i * rstr), 0);
+                }
+            }
         }
     };
     auto use = [&](const uint32_t (&y)[BL], int lim) {
 #pragma unroll
-        for (int e = 0; e < BL; ++e) f(y[e], e < lim);
+        for (int q = 0; q < BL / GQ; ++q) {
+            if (q * GQ < lim) {
+#pragma unroll
+                for (int e = q * GQ; e < q * GQ + GQ; ++e) f(y[e], e < lim);
+            }
+        }
     };
     const int nfull = w / BL, rem = w - nfull * BL;
     uint32_t ya[BL], yb[BL];
     load(ya, 0);
     int b = 0;
     for (; b + 2 <= nfull; b += 2) {
-        load(yb, (b + 1) * BL);
+        load_full(yb, (b + 1) * BL);
         use(ya, BL);
         load(ya, (b + 2) * BL);
         use(yb, BL);
@@ -180,9 +201,15 @@ __device__ __forceinline__ void window_pass(__amdgpu_buffer_rsrc_t R, uint32_t v
     }
     if (c < w) {
         uint32_t y[BL];
+        const int lim = w - c;
 #pragma unroll
-        for (int e = 0; e < BL; ++e) y[e] = bk[min(c + e, wm1)];
-        use(y, w - c);
+        for (int q = 0; q < BL / GQ; ++q) {
+            if (q * GQ < lim) {
+#pragma unroll
+                for (int e = q * GQ; e < q * GQ + GQ; ++e) y[e] = bk[min(c + e, wm1)];
+            }
+        }
+        use(y, lim);
     }
 }
 
