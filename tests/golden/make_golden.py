@@ -33,6 +33,11 @@ SWEEPS = {
     # every candidate length 64, 96, ..., 512 with l = m/2 and K = 6
     "regimes6_n250000_sweep": dict(series=lambda: synth.regime_series(250_000, 3, synth.SHAPES6).x,
                                    m_list=list(range(64, 513, 32)), K=6),
+    # the same series with five of those lengths, from the shortest to the
+    # longest (the oracle needs about an hour on 7 processes for these five,
+    # against about ten for all fifteen)
+    "regimes6_n250000_sweep5": dict(series=lambda: synth.regime_series(250_000, 3, synth.SHAPES6).x,
+                                    m_list=[64, 128, 224, 480, 512], K=6),
 }
 
 _X = None

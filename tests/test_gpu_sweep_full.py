@@ -1,6 +1,7 @@
-"""The length sweep at full size (250 000-point six-shape series, m = 64, 96,
-.., 512, l = m/2, K = 6) against the oracle's stored results
-(tests/golden/sweep_regimes6_n250000_sweep.json, written by
+"""The length sweep at full size (the 250 000-point six-shape series of the
+sweep benchmark, l = m/2, K = 6, over five of its fifteen lengths: m = 64,
+128, 224, 480, 512) against the oracle's stored results
+(tests/golden/sweep_regimes6_n250000_sweep5.json, written by
 tests/golden/make_golden.py from oracle/ only).
 
 Per length, the GPU's snippets are checked step by step against the oracle's
@@ -23,7 +24,7 @@ from greedy_bounds import areas_from_profiles
 from paper_2401_13680_amd import api, synth
 
 pytestmark = pytest.mark.gpu
-GOLD = os.path.join(os.path.dirname(__file__), "golden", "sweep_regimes6_n250000_sweep.json")
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "sweep_regimes6_n250000_sweep5.json")
 
 
 def _area(M, row):
