@@ -37,10 +37,13 @@
 //      counts the values below the bracket and collects the ones inside it
 //      (adjacent windows share all but a few of their 2w values, so the k-th
 //      value rarely leaves the bracket), sorts the few collected values and
-//      takes the next bracket from them.  Windows whose bracket misses are
-//      solved by the 64 lanes of the wave together, one window at a time, so a
-//      rare miss costs the wave a short cooperative step instead of stalling
-//      every lane.  The result is exact either way.
+//      takes the next bracket from them.  A window whose bracket misses gets a
+//      second pass with a bracket re-aimed from the first (taken by the
+//      missing lanes of a wave together when there are a few of them); what
+//      still misses is solved by the 64 lanes of the wave together, one window
+//      at a time (by counting ranks for short windows, a radix select for
+//      longer ones), so a rare miss costs the wave a short step instead of
+//      stalling every lane.  The result is exact either way.
 //
 // Arithmetic of a cell depends only on the query's data, the column and the
 // window offset inside the tile, never on the query's position, so identical
