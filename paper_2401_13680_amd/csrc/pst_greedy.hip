@@ -195,6 +195,20 @@ __global__ void k_gather(SweepGather G) {
     }
 }
 
+// One block per request of a served batch (see ResultPack).
+__global__ void k_pack_results(ResultPack P) {
+    const int i = blockIdx.x, K = P.K[i];
+    double *h = P.out + P.off[i];
+    for (int t = threadIdx.x; t < 4; t += blockDim.x) h[t] = P.misc[i][t];
+    int32_t *hp = (int32_t *)(h + 4), *hc = (int32_t *)(h + 4 + 2 * K);
+    for (int t = threadIdx.x; t < K; t += blockDim.x) {
+        hp[t] = P.pick[i][t];
+        h[4 + K + t] = P.area[i][t];
+        hc[t] = P.count[i][t];
+    }
+    if (threadIdx.x == 0) *(uint32_t *)(h + 4 + 3 * K) = *P.dmax[i];
+}
+
 inline int grid_for(int64_t n) {
     int64_t b = (n + GT - 1) / GT;
     return (int)(b < 2048 ? (b > 0 ? b : 1) : 2048);
@@ -278,6 +292,12 @@ hipError_t launch_owner_batch(const GreedyJob *g, int n, hipStream_t st) {
 }
 
 hipError_t launch_owner(const GreedyJob &g, hipStream_t st) { return launch_owner_batch(&g, 1, st); }
+
+hipError_t launch_pack_results(const ResultPack &r, hipStream_t st) {
+    if (r.n < 1 || r.n > kMaxJobs) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_pack_results, dim3(r.n), dim3(64), 0, st, r);
+    return hipGetLastError();
+}
 
 hipError_t launch_gather(const SweepGather &g, hipStream_t st) {
     hipLaunchKernelGGL(k_gather, dim3(1), dim3(256), 0, st, g);

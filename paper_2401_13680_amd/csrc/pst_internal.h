@@ -138,6 +138,23 @@ struct SweepGather {
 };
 hipError_t launch_gather(const SweepGather &g, hipStream_t st);
 
+// A served request's results packed for one copy to the host, at
+// out[off[i]]: the 4 statistics words (misc), K picks (int32), K areas
+// (double), K neighbour counts (int32) and max D (float bits), each part at
+// the double offset 4, 4+K, 4+2K, 4+3K.
+struct ResultPack {
+    int32_t n;
+    int32_t K[kMaxJobs];
+    int64_t off[kMaxJobs];
+    const double *misc[kMaxJobs];
+    const int32_t *pick[kMaxJobs];
+    const double *area[kMaxJobs];
+    const int32_t *count[kMaxJobs];
+    const uint32_t *dmax[kMaxJobs];
+    double *out;
+};
+hipError_t launch_pack_results(const ResultPack &r, hipStream_t st);
+
 // Labelling score: owner array of K snippets against true classes.
 struct LabelJob {
     const int32_t *owner;  // [n-m+1] greedy rank of each window's nearest snippet
