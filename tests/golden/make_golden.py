@@ -38,6 +38,9 @@ SWEEPS = {
     # against about ten for all fifteen)
     "regimes6_n250000_sweep5": dict(series=lambda: synth.regime_series(250_000, 3, synth.SHAPES6).x,
                                     m_list=[64, 128, 224, 480, 512], K=6),
+    # ten of them: every length up to 288, and 480, 512
+    "regimes6_n250000_sweep10": dict(series=lambda: synth.regime_series(250_000, 3, synth.SHAPES6).x,
+                                     m_list=[64, 96, 128, 160, 192, 224, 256, 288, 480, 512], K=6),
 }
 
 _X = None
