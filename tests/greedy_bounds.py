@@ -28,7 +28,9 @@ def _area(M, row):
 
 
 def _bound(Mg, Mr, rg, rr):
-    dM = np.where(np.isinf(Mg) & np.isinf(Mr), 0.0, np.abs(Mg - Mr))
+    # before the first pick both curves are +inf: no difference there
+    both = np.isinf(Mg) & np.isinf(Mr)
+    dM = np.abs(np.where(both, 0.0, Mg) - np.where(both, 0.0, Mr))
     return float(np.sum(np.maximum(dM, np.abs(rg - rr))))
 
 
