@@ -365,7 +365,8 @@ int pst_label_f1(pst_ctx *ctx, const int32_t *owner_dev, int64_t n, int32_t m, i
  *                          sweep's profile launch on first use of a shape
  *                          bucket [0, 1]; the choice is kept per process and,
  *                          if the environment variable PST_AUTOTUNE_CACHE names
- *                          a file, appended there and read back later
+ *                          a file, appended there and read back later (a grid
+ *                          read back never exceeds the workspace's slots)
  *   PST_OPT_PROFILE_GRID   persistent workgroups of the sweep launch [0 = all
  *                          that are resident at once]
  *   PST_OPT_DYNAMIC_TILES  hand tiles out from a device counter [1, 0]

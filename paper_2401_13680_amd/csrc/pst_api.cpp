@@ -843,7 +843,11 @@ int autotune(pst_ctx *c, const SweepPlan &P, const double *T, char *ws, TuneVal 
         tune_load_locked();
         auto it = g_tuned.find(key);
         if (it != g_tuned.end()) {
+            // a line of the cache file may come from another build: never more
+            // workgroups than the workspace has scratch slots for
             *out = it->second;
+            out->grid = std::max(1, std::min(out->grid, P.grid));
+            out->dynamic = out->dynamic != 0;
             return PST_OK;
         }
     }

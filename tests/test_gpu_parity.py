@@ -285,6 +285,44 @@ def test_sweep_autotune_same_result(tmp_path, monkeypatch):
     assert _sweep_key(a) == _sweep_key(b)
 
 
+_TUNED_SWEEP = (
+    "import json, torch\n"
+    "from paper_2401_13680_amd import api, synth\n"
+    "x = synth.regime_series(5000, 14, len_range=(500, 1500)).x\n"
+    "r = api.select_length(torch.from_numpy(x).cuda(), [48, 64, 80], 2, autotune=True)\n"
+    "print(json.dumps([r['m_best'], list(r['scores']),\n"
+    "                  [(q['segment'], q['greedy_rank'], q['area_after']) for q in r['records']]]))\n")
+
+
+def test_cached_grid_past_the_workspace_is_clamped(tmp_path):
+    """A line of the tuning cache file may come from another build: a cached
+    persistent grid larger than the sweep's workspace has scratch slots for is
+    clamped to the plan's grid.  The second process takes the cached line
+    (it appends none) and returns the first one's result exactly."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    cache = tmp_path / "tune.txt"
+    env = dict(os.environ, PST_AUTOTUNE_CACHE=str(cache))
+
+    def run():
+        p = subprocess.run([sys.executable, "-c", _TUNED_SWEEP], cwd=root, env=env,
+                           capture_output=True, text=True, timeout=300)
+        assert p.returncode == 0, p.stderr[-2000:]
+        return json.loads(p.stdout.strip().splitlines()[-1])
+
+    first = run()
+    lines = cache.read_text().splitlines()
+    grid_lines = [q for q in lines if q.split()[0] != "geo"]
+    assert grid_lines, lines
+    # "arch wmax tiles_log2 grid dynamic ms": the grid far past any workspace
+    cache.write_text("".join(" ".join(f[:3] + ["1000000"] + f[4:]) + "\n" if f[0] != "geo" else q + "\n"
+                             for q in lines for f in [q.split()]))
+    second = run()
+    assert len(cache.read_text().splitlines()) == len(lines)
+    assert second == first
+
+
 def test_server_results_equal_alone_and_in_mix():
     """Requests of different n, m and K submitted together overlap on the
     device; each result equals the same request run alone with pst_snippets,
