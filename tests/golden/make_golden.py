@@ -35,13 +35,16 @@ SWEEPS = {
                                    m_list=list(range(64, 513, 32)), K=6),
     # the same series with five of those lengths, from the shortest to the
     # longest (the oracle needs about an hour on 7 processes for these five,
-    # about four for all fifteen)
+    # about five for all fifteen)
     "regimes6_n250000_sweep5": dict(series=lambda: synth.regime_series(250_000, 3, synth.SHAPES6).x,
                                     m_list=[64, 128, 224, 480, 512], K=6),
     # ten of them: every length up to 288, and 480, 512 (about two and a half
     # hours on 7 processes)
     "regimes6_n250000_sweep10": dict(series=lambda: synth.regime_series(250_000, 3, synth.SHAPES6).x,
                                      m_list=[64, 96, 128, 160, 192, 224, 256, 288, 480, 512], K=6),
+    # twelve: those ten and 416, 448 (the two take about an hour more)
+    "regimes6_n250000_sweep12": dict(series=lambda: synth.regime_series(250_000, 3, synth.SHAPES6).x,
+                                     m_list=[64, 96, 128, 160, 192, 224, 256, 288, 416, 448, 480, 512], K=6),
 }
 
 _X = None

@@ -1,10 +1,10 @@
 """The length sweep at full size (the 250 000-point six-shape series of the
 sweep benchmark, l = m/2, K = 6, over all fifteen of its lengths, m = 64 ..
-512 step 32, or over ten of them, m = 64 .. 288 and 480, 512, or over five,
-m = 64, 128, 224, 480, 512) against the oracle's stored results
-(tests/golden/sweep_regimes6_n250000_sweep.json, ..._sweep10.json or
-..._sweep5.json, whichever is the longest there, written by
-tests/golden/make_golden.py from oracle/ only).
+512 step 32, or over twelve of them, m = 64 .. 288 and 416 .. 512, or ten,
+m = 64 .. 288 and 480, 512, or five, m = 64, 128, 224, 480, 512) against the
+oracle's stored results (tests/golden/sweep_regimes6_n250000_sweep.json,
+..._sweep12.json, ..._sweep10.json or ..._sweep5.json, whichever is the
+longest there, written by tests/golden/make_golden.py from oracle/ only).
 
 Per length, the GPU's snippets are checked step by step against the oracle's
 pick and runner-up: while the GPU's picks equal the oracle's, the two
@@ -29,6 +29,7 @@ pytestmark = pytest.mark.gpu
 _G = os.path.join(os.path.dirname(__file__), "golden")
 # the longest list of lengths that has been written
 GOLD = next((os.path.join(_G, f) for f in ("sweep_regimes6_n250000_sweep.json",
+                                           "sweep_regimes6_n250000_sweep12.json",
                                            "sweep_regimes6_n250000_sweep10.json",
                                            "sweep_regimes6_n250000_sweep5.json")
              if os.path.exists(os.path.join(_G, f))), os.path.join(_G, "sweep_regimes6_n250000_sweep5.json"))
