@@ -6,8 +6,9 @@ series, Poisson arrivals at 20 requests/s, n log-uniform in [1e4, 5e5], m
 uniform in {64, 128, 256, 512, 1024}, l = m/2, K uniform in 3..5.  A step is
 ten requests of the stream, so --steps 20 serves the 200-request stream.
 Inputs are resident in HBM (pst_submit_device) when the timed region starts.
-`value` = distance-matrix cells of the stream / time to serve all of it
-submitted at once (continuous batching); the plain per-request path
+The whole stream (all steps' requests) is submitted at once and served with
+continuous batching; `value` = its distance-matrix cells / the time to serve
+it, and ms_per_step = that time / steps.  The plain per-request path
 (pst_snippets one request after another) is measured beside it; p50/p99 come
 from a replay at the stream's own arrival times.
 cells = nseg * (m-l+1) * (n-l+1) per request.
@@ -574,8 +575,9 @@ def serve_bench(args):
                config=dict(workload=f"poisson20_serving_{nreq}", requests=nreq, requests_per_step=10,
                            n="log-uniform [1e4, 5e5]", m=[64, 128, 256, 512, 1024], l="m/2", K="3..5",
                            rate_per_s=20.0, cells=cells,
-                           step="ten requests of the stream, all submitted at once with series in HBM, "
-                                "served with continuous batching"),
+                           step="ten requests' share of the stream: all the steps' requests are submitted "
+                                "at once with series in HBM and served with continuous batching; "
+                                "ms_per_step is their time over the steps"),
                latency_ms=dict(p50=float(np.percentile(lat, 50)), p99=float(np.percentile(lat, 99)),
                                mean=float(np.mean(lat)), replay_s=span,
                                offered_cells_per_s=offered,
